@@ -1,0 +1,177 @@
+/*
+ * pic.h -- C ABI of the MI355X (gfx950) implicit 2D3V particle-in-cell particle stage.
+ *
+ * The library implements one cycle of the implicit PIC method of Petrov & Davis
+ * ("Parallelization of an implicit algorithm for multi-dimensional particle-in-cell
+ * simulations"), Sec. 2 and Sec. 3.3, on one GPU:
+ *   field solve   Eq. (4) per node with the x-boundary conditions and the x = 0 source
+ *                 (Steps 3-6), E-bar = (E^n + E^{n+1})/2, then Eq. (5) (Steps 8-9);
+ *   particles     gather E-bar and B, implicit relativistic push (Eq. (2) solved for the
+ *                 momentum, particles pushed once per cycle), position advance, and the
+ *                 deposit of the implicit source moments S-hat and delta-j of Eq. (3)
+ *                 (Step 1) plus the species densities, at the new positions;
+ *   sort          stable sort of every species by cell, dropping particles that left an
+ *                 absorbing boundary (the one-GPU counterpart of moving particles to the
+ *                 processor that owns them, Sec. 3.1 and the end of Sec. 3.3).
+ *
+ * Conventions shared by every call:
+ *   - the simulation plane is (x, z) with d/dy = 0 and three momentum components;
+ *   - units c = eps0 = mu0 = 1 (so B = H); time in 1/omega_r, length in c/omega_r,
+ *     momentum u = p/(m c), charge in e, mass in m_e;
+ *   - positions are in cell units: cell (i, k) covers [i, i+1) x [k, k+1);
+ *   - E lives on grid nodes and H at cell centres (Sec. 2, last paragraph; Sec. 3.2 (3));
+ *     a periodic axis with N cells has N nodes (node N is node 0), an absorbing axis N + 1;
+ *   - every 2D array is stored with x fastest: node (i, k) at k * nodes_x + i, cell (i, k)
+ *     at k * nx + i;
+ *   - moment planes (Step 1 and Fig. 1: S-hat and delta-j on the nodes), each one node
+ *     array: 0..8 S-hat row-major (S_xx S_xy S_xz S_yx ... S_zz), 9..11 delta-j,
+ *     12 + s density of species s;
+ *   - state after k cycles: positions x^{k+1/2}, momenta u^k, E^k, H^{k+1/2}, t = k dt.
+ *
+ * Ownership: every pointer argument is a HOST pointer owned by the caller; the library
+ * copies from or into it during the call and keeps nothing.  The context owns all device
+ * memory.  Every call returns a pic_status; on failure pic_last_error() gives a message and
+ * the context state is unchanged unless stated.  One context must not be used from two host
+ * threads at once; separate contexts are independent.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pic_ctx pic_ctx;
+
+typedef enum {
+  PIC_OK = 0,
+  PIC_ERR_ARG = 1,      /* invalid argument or descriptor (includes dt > min(dx, dz)) */
+  PIC_ERR_OOM = 2,      /* device allocation failed */
+  PIC_ERR_DEVICE = 3,   /* a HIP call failed */
+  PIC_ERR_STATE = 4,    /* call out of order (e.g. step before any particles were loaded) */
+  PIC_ERR_RANGE = 5,    /* particle position outside the domain or non-finite input */
+  PIC_ERR_OVERFLOW = 6  /* the device raised an overflow flag during a step (see pic_info) */
+} pic_status;
+
+enum { PIC_BC_PERIODIC = 0, PIC_BC_ABSORBING = 1 };
+enum { PIC_PREC_FP64 = 0, PIC_PREC_MIXED = 1 };
+enum { PIC_MAX_SPECIES = 8 };
+
+/* Device overflow flags reported in pic_info.overflow_flags. */
+enum {
+  PIC_FLAG_ORDER = 1u,      /* a particle was not in the cell its sorted slot says */
+  PIC_FLAG_NONFINITE = 2u,  /* a pushed momentum or position was not finite */
+  PIC_FLAG_JUMP = 4u,       /* a particle moved by more than one cell in one cycle */
+  PIC_FLAG_SLOT = 8u        /* a sort destination fell outside the particle array */
+};
+
+typedef struct {
+  int32_t nx, nz;            /* cells along x and z, each >= 1 */
+  double dx, dz, dt;         /* cell sizes and time step; dt <= min(dx, dz) is required */
+  int32_t bc_x, bc_z;        /* PIC_BC_*; bc_z must be PIC_BC_PERIODIC */
+  int32_t precision;         /* PIC_PREC_FP64 or PIC_PREC_MIXED */
+  int32_t n_species;         /* number of species slots S, 1..PIC_MAX_SPECIES */
+  double e0[3], h0[3];       /* uniform initial E (nodes) and H (cell centres) */
+  /* E_y source at x = 0 (absorbing x only; a0 = 0 switches it off):
+   *   a0 sin(omega (t - x)) exp(-(z - z_center)^2 / (2 sigma_z^2))
+   *      exp(-2 ln 2 ((t - x - t_center) / fwhm_t)^2)                                  */
+  double laser_a0, laser_omega, laser_sigma_z, laser_z_center, laser_fwhm_t, laser_t_center;
+  int32_t allow_cfl_violation; /* must be 0: the cell sort relies on moves of < 1 cell */
+  int32_t track_ids;         /* 1: carry a 64-bit label per particle through every sort */
+  int32_t tile_x, tile_z;    /* cells per particle tile; 0 picks them from the load */
+  int32_t device;            /* HIP device ordinal */
+  int32_t reserved[7];       /* must be zero */
+} pic_grid_desc;
+
+typedef struct {
+  int64_t step;              /* cycles done */
+  double t;                  /* step * dt */
+  int32_t n_species, nodes_x, nodes_z, cells_x, cells_z;
+  int32_t tile_x, tile_z, precision;
+  int64_t alive[PIC_MAX_SPECIES];     /* particles held per species */
+  int64_t absorbed[PIC_MAX_SPECIES];  /* particles removed at absorbing boundaries */
+  uint32_t overflow_flags;   /* PIC_FLAG_* raised since the last pic_load_* call */
+  int64_t device_bytes;      /* device memory held by the context */
+} pic_info;
+
+typedef struct {
+  int64_t steps;             /* cycles timed since profiling was enabled */
+  int64_t particle_launches; /* launches of the fused gather-push-deposit kernel */
+  double particle_ms;        /* their summed duration (HIP events on the context's stream) */
+  int64_t field_launches;    /* field-solve kernel pairs */
+  double field_ms;
+  int64_t sort_launches;     /* scan + rank/scatter kernel sequences */
+  double sort_ms;
+  double step_ms;            /* whole cycles, first kernel start to last kernel end */
+} pic_profile;
+
+/* Create a context: validate the descriptor, allocate E, E-bar, H (two time levels) and
+ * the moment planes on the device, and set E = e0, H = h0, t = 0 (Sec. 3.2 (1), (3)).
+ * Errors: PIC_ERR_ARG for an invalid descriptor, PIC_ERR_OOM, PIC_ERR_DEVICE.  On error
+ * *out is NULL. */
+pic_status pic_init_grid(const pic_grid_desc *desc, pic_ctx **out);
+
+/* Place n particles of species s (Sec. 3.2 (2)): charge q, mass m, density carried per
+ * particle w (the n_alpha of Sec. 2), positions x^{k+1/2} in cell units and momenta u^k.
+ * Replaces whatever species s held.  The particles are stably sorted by cell (input order
+ * breaks ties), and the moments M^{k+1/2} of all species are deposited again.  When
+ * track_ids is set, particle a gets label a.  Errors: PIC_ERR_ARG (s out of range, n < 0,
+ * m <= 0, q or w not finite, NULL array with n > 0), PIC_ERR_RANGE (a position outside
+ * [0, nx) x [0, nz) or a non-finite value), PIC_ERR_OOM. */
+pic_status pic_load_particles(pic_ctx *ctx, int32_t species, double q, double m, double w,
+                              int64_t n, const double *xi_x, const double *xi_z,
+                              const double *ux, const double *uy, const double *uz);
+
+/* Replace E^k ([3][nodes]) and H^{k+1/2} ([3][cells]); either may be NULL to keep it.
+ * The moments are deposited again since they depend on H at the particles.
+ * Errors: PIC_ERR_RANGE for a non-finite value. */
+pic_status pic_load_fields(pic_ctx *ctx, const double *e, const double *h);
+
+/* Set the cycle counter and time t = step * dt (used by the x = 0 source). */
+pic_status pic_set_step(pic_ctx *ctx, int64_t step);
+
+/* Advance nsteps cycles (Sec. 3.3): field solve, gather-push-deposit, sort.  Work is queued
+ * on the context's stream; the call returns without waiting.  Errors: PIC_ERR_STATE if no
+ * species is loaded, PIC_ERR_ARG for nsteps < 0, PIC_ERR_DEVICE. */
+pic_status pic_step(pic_ctx *ctx, int32_t nsteps);
+
+/* Copy the moment planes M^{k+1/2} ((12 + S) * nodes doubles) into out; len is the size of
+ * out in doubles.  Waits for the stream.  Errors: PIC_ERR_ARG if len is too small. */
+pic_status pic_read_moments(pic_ctx *ctx, double *out, int64_t len);
+
+/* Copy E^k ([3][nodes]) and H^{k+1/2} ([3][cells]); either pointer may be NULL. */
+pic_status pic_read_fields(pic_ctx *ctx, double *e, double *h);
+
+/* Copy species s in its current (cell-sorted) order.  *n_inout holds the capacity of the
+ * arrays on entry and the particle count on return; PIC_ERR_ARG if the capacity is too
+ * small (then *n_inout is the count needed).  id may be NULL; it needs track_ids. */
+pic_status pic_read_particles(pic_ctx *ctx, int32_t species, int64_t *n_inout, double *xi_x,
+                              double *xi_z, double *ux, double *uy, double *uz, int64_t *id);
+
+/* Sizes, counters and device flags (waits for the stream). */
+pic_status pic_get_info(pic_ctx *ctx, pic_info *info);
+
+/* Queue the context's work on an existing HIP stream (hipStream_t passed as void *), or on
+ * the context's own stream when NULL.  The stream must outlive its use by the context. */
+pic_status pic_set_stream(pic_ctx *ctx, void *stream);
+
+/* Wait until all queued work of the context has finished. */
+pic_status pic_sync(pic_ctx *ctx);
+
+/* Per-kernel timing with HIP events recorded on the context's stream (on = 1 starts a new
+ * measurement, 0 stops); read the sums with pic_profile_read (waits for the stream). */
+pic_status pic_profile_enable(pic_ctx *ctx, int32_t on);
+pic_status pic_profile_read(pic_ctx *ctx, pic_profile *out);
+
+/* Message for the last failed call on this context (or of pic_init_grid when ctx is NULL). */
+const char *pic_last_error(const pic_ctx *ctx);
+
+/* Release the context and all its device memory.  NULL is allowed. */
+void pic_destroy(pic_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIC_H */

@@ -1,0 +1,253 @@
+"""Thin ctypes binding of include/pic.h (argument marshalling only).
+
+Every computation happens in the HIP library ``libpic.so`` built in-tree by ``build.py``.
+There is no fallback: if the library is missing or fails to load, every call raises.
+PyTorch is imported first so that the library and torch share one HIP runtime in the
+process; it is otherwise only used to pass a torch stream to ``set_stream``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libpic.so")
+
+PIC_OK = 0
+STATUS = {0: "PIC_OK", 1: "PIC_ERR_ARG", 2: "PIC_ERR_OOM", 3: "PIC_ERR_DEVICE",
+          4: "PIC_ERR_STATE", 5: "PIC_ERR_RANGE", 6: "PIC_ERR_OVERFLOW"}
+MAX_SPECIES = 8
+EXPORTED = ["pic_init_grid", "pic_load_particles", "pic_load_fields", "pic_set_step", "pic_step",
+            "pic_read_moments", "pic_read_fields", "pic_read_particles", "pic_get_info",
+            "pic_set_stream", "pic_sync", "pic_profile_enable", "pic_profile_read",
+            "pic_last_error", "pic_destroy"]
+
+
+class PicError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("nz", C.c_int32), ("dx", C.c_double), ("dz", C.c_double),
+                ("dt", C.c_double), ("bc_x", C.c_int32), ("bc_z", C.c_int32),
+                ("precision", C.c_int32), ("n_species", C.c_int32),
+                ("e0", C.c_double * 3), ("h0", C.c_double * 3),
+                ("laser_a0", C.c_double), ("laser_omega", C.c_double),
+                ("laser_sigma_z", C.c_double), ("laser_z_center", C.c_double),
+                ("laser_fwhm_t", C.c_double), ("laser_t_center", C.c_double),
+                ("allow_cfl_violation", C.c_int32), ("track_ids", C.c_int32),
+                ("tile_x", C.c_int32), ("tile_z", C.c_int32), ("device", C.c_int32),
+                ("reserved", C.c_int32 * 7)]
+
+
+class Info(C.Structure):
+    _fields_ = [("step", C.c_int64), ("t", C.c_double), ("n_species", C.c_int32),
+                ("nodes_x", C.c_int32), ("nodes_z", C.c_int32), ("cells_x", C.c_int32),
+                ("cells_z", C.c_int32), ("tile_x", C.c_int32), ("tile_z", C.c_int32),
+                ("precision", C.c_int32), ("alive", C.c_int64 * MAX_SPECIES),
+                ("absorbed", C.c_int64 * MAX_SPECIES), ("overflow_flags", C.c_uint32),
+                ("device_bytes", C.c_int64)]
+
+
+class Profile(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("particle_launches", C.c_int64),
+                ("particle_ms", C.c_double), ("field_launches", C.c_int64),
+                ("field_ms", C.c_double), ("sort_launches", C.c_int64), ("sort_ms", C.c_double),
+                ("step_ms", C.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libpic.so; raises if it is missing (no CPU fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_1308_2590_amd/build.py "
+                           "(or __graft_entry__.build())")
+    try:
+        import torch  # noqa: F401  -- one HIP runtime per process, shared with torch
+    except ImportError:
+        pass
+    lib = C.CDLL(path)
+    P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "pic_init_grid": ([C.POINTER(GridDesc), C.POINTER(P)], C.c_int),
+        "pic_load_particles": ([P, I32, D, D, D, I64, P, P, P, P, P], C.c_int),
+        "pic_load_fields": ([P, P, P], C.c_int),
+        "pic_set_step": ([P, I64], C.c_int),
+        "pic_step": ([P, I32], C.c_int),
+        "pic_read_moments": ([P, P, I64], C.c_int),
+        "pic_read_fields": ([P, P, P], C.c_int),
+        "pic_read_particles": ([P, I32, C.POINTER(I64), P, P, P, P, P, P], C.c_int),
+        "pic_get_info": ([P, C.POINTER(Info)], C.c_int),
+        "pic_set_stream": ([P, P], C.c_int),
+        "pic_sync": ([P], C.c_int),
+        "pic_profile_enable": ([P, I32], C.c_int),
+        "pic_profile_read": ([P, C.POINTER(Profile)], C.c_int),
+        "pic_last_error": ([P], C.c_char_p),
+        "pic_destroy": ([P], None),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def make_desc(grid, *, track_ids=False, tile=(0, 0), device=0, precision=None) -> GridDesc:
+    """pic_grid_desc from any object with the grid attributes (nx, nz, dx, dz, dt, bc_x, ...)."""
+    d = GridDesc()
+    d.nx, d.nz = int(grid.nx), int(grid.nz)
+    d.dx, d.dz, d.dt = float(grid.dx), float(grid.dz), float(grid.dt)
+    d.bc_x, d.bc_z = int(grid.bc_x), int(grid.bc_z)
+    d.precision = int(getattr(grid, "precision", 0) if precision is None else precision)
+    d.n_species = int(grid.n_species)
+    for r in range(3):
+        d.e0[r] = float(grid.e0[r])
+        d.h0[r] = float(grid.h0[r])
+    d.laser_a0, d.laser_omega = float(grid.laser_a0), float(grid.laser_omega)
+    d.laser_sigma_z, d.laser_z_center = float(grid.laser_sigma_z), float(grid.laser_z_center)
+    d.laser_fwhm_t, d.laser_t_center = float(grid.laser_fwhm_t), float(grid.laser_t_center)
+    d.allow_cfl_violation = int(getattr(grid, "allow_cfl_violation", 0))
+    d.track_ids = 1 if track_ids else 0
+    d.tile_x, d.tile_z = int(tile[0]), int(tile[1])
+    d.device = int(device)
+    return d
+
+
+class Context:
+    """One pic_ctx.  Method names follow the C ABI without the ``pic_`` prefix."""
+
+    def __init__(self, grid, *, track_ids=False, tile=(0, 0), device=0, precision=None):
+        self.lib = load_library()
+        self.desc = make_desc(grid, track_ids=track_ids, tile=tile, device=device,
+                              precision=precision)
+        h = C.c_void_p()
+        st = self.lib.pic_init_grid(C.byref(self.desc), C.byref(h))
+        if st != PIC_OK:
+            raise PicError(st, self.lib.pic_last_error(None).decode())
+        self.h = h
+        self.S = self.desc.n_species
+        self.nxn = self.desc.nx + (1 if self.desc.bc_x == 1 else 0)
+        self.nzn = self.desc.nz
+        self.nx, self.nz = self.desc.nx, self.desc.nz
+
+    def _check(self, st):
+        if st != PIC_OK:
+            raise PicError(st, self.lib.pic_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pic_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- the ABI --------------------------------------------------------------------------
+    def load_particles(self, s, q, m, w, xi_x, xi_z, ux, uy, uz):
+        arrs = [_f64(a) for a in (xi_x, xi_z, ux, uy, uz)]
+        n = arrs[0].shape[0]
+        if any(a.shape[0] != n for a in arrs):
+            raise ValueError("particle arrays differ in length")
+        self._check(self.lib.pic_load_particles(self.h, int(s), float(q), float(m), float(w), n,
+                                                *[_p(a) for a in arrs]))
+
+    def load_fields(self, e=None, h=None):
+        e = None if e is None else _f64(e).reshape(-1)
+        h = None if h is None else _f64(h).reshape(-1)
+        if e is not None and e.size != 3 * self.nxn * self.nzn:
+            raise ValueError("E must have 3 * nodes values")
+        if h is not None and h.size != 3 * self.nx * self.nz:
+            raise ValueError("H must have 3 * cells values")
+        self._check(self.lib.pic_load_fields(self.h, _p(e), _p(h)))
+
+    def set_step(self, step):
+        self._check(self.lib.pic_set_step(self.h, int(step)))
+
+    def step(self, nsteps=1):
+        self._check(self.lib.pic_step(self.h, int(nsteps)))
+
+    def read_moments(self):
+        out = np.empty((12 + self.S, self.nzn, self.nxn))
+        self._check(self.lib.pic_read_moments(self.h, _p(out), out.size))
+        return out
+
+    def read_fields(self):
+        e = np.empty((3, self.nzn, self.nxn))
+        h = np.empty((3, self.nz, self.nx))
+        self._check(self.lib.pic_read_fields(self.h, _p(e), _p(h)))
+        return e, h
+
+    def read_particles(self, s, ids=None):
+        if ids is None:
+            ids = bool(self.desc.track_ids)
+        info = self.get_info()
+        n = int(info["alive"][s])
+        cap = C.c_int64(n)
+        out = {k: np.empty(n) for k in ("xi_x", "xi_z", "ux", "uy", "uz")}
+        idv = np.empty(n, dtype=np.int64) if ids else None
+        self._check(self.lib.pic_read_particles(self.h, int(s), C.byref(cap), _p(out["xi_x"]),
+                                                _p(out["xi_z"]), _p(out["ux"]), _p(out["uy"]),
+                                                _p(out["uz"]), _p(idv)))
+        if idv is not None:
+            out["id"] = idv
+        return out
+
+    def get_info(self):
+        inf = Info()
+        self._check(self.lib.pic_get_info(self.h, C.byref(inf)))
+        S = inf.n_species
+        return {"step": inf.step, "t": inf.t, "n_species": S, "nodes_x": inf.nodes_x,
+                "nodes_z": inf.nodes_z, "cells_x": inf.cells_x, "cells_z": inf.cells_z,
+                "tile": (inf.tile_x, inf.tile_z), "precision": inf.precision,
+                "alive": [inf.alive[s] for s in range(S)],
+                "absorbed": [inf.absorbed[s] for s in range(S)],
+                "overflow_flags": inf.overflow_flags, "device_bytes": inf.device_bytes}
+
+    def set_stream(self, stream=None):
+        """stream: a torch.cuda.Stream, a raw hipStream_t as int, or None (own stream)."""
+        ptr = None
+        if stream is not None:
+            ptr = int(getattr(stream, "cuda_stream", stream))
+        self._check(self.lib.pic_set_stream(self.h, C.c_void_p(ptr) if ptr else None))
+
+    def sync(self):
+        self._check(self.lib.pic_sync(self.h))
+
+    def profile_enable(self, on=True):
+        self._check(self.lib.pic_profile_enable(self.h, 1 if on else 0))
+
+    def profile_read(self):
+        p = Profile()
+        self._check(self.lib.pic_profile_read(self.h, C.byref(p)))
+        return {f: getattr(p, f) for f, _ in Profile._fields_}
+
+
+def init_grid(grid, **kw) -> Context:
+    return Context(grid, **kw)

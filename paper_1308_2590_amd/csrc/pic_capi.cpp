@@ -1,0 +1,637 @@
+// Host side of the C ABI declared in include/pic.h: context life cycle, device buffers,
+// particle loading, the per-cycle kernel sequence and read-back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pic.h"
+#include "pic_internal.h"
+
+namespace {
+
+thread_local std::string g_init_error;
+
+struct SpeciesState {
+  bool loaded = false;
+  double q = 0, m = 1, w = 0;
+  int64_t cap = 0;         // slots allocated
+  int64_t n_loaded = 0;    // particles given at the last load
+  double *buf[2][5] = {};  // two copies of the state; perm maps sorted slot -> location
+  int64_t *ids[2] = {};
+  int32_t *perm[2] = {};
+  int32_t *cs[2] = {};     // cell start offsets [ncells + 1]
+  uint8_t *code = nullptr;
+  int32_t *cnt = nullptr;  // [9][ncells]
+  int32_t *bsum = nullptr;
+};
+
+struct ProfEvents {
+  hipEvent_t ev[4];  // step start, after field solve, after particles, after sort
+};
+
+}  // namespace
+
+struct pic_ctx {
+  pic_grid_desc d{};
+  pic::GridArgs g{};
+  pic::LaserArgs laser{};
+  pic::TileArgs tiles{};
+  int S = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t own_stream = nullptr;
+  double *E[2] = {}, *Ebar = nullptr, *H[2] = {}, *M = nullptr;
+  int ecur = 0, hcur = 0, cur = 0;
+  SpeciesState sp[PIC_MAX_SPECIES];
+  uint32_t *flags = nullptr;
+  int64_t step = 0;
+  int64_t bytes = 0;
+  int32_t n_scan_blocks = 0;
+  std::string err;
+  // profiling
+  bool prof_on = false;
+  std::vector<ProfEvents> prof_ev;
+  size_t prof_used = 0;
+  pic_profile prof_acc{};
+};
+
+namespace {
+
+pic_status fail(pic_ctx *c, pic_status st, const std::string &msg) {
+  if (c)
+    c->err = msg;
+  else
+    g_init_error = msg;
+  return st;
+}
+
+pic_status hip_fail(pic_ctx *c, hipError_t e, const char *what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(c, e == hipErrorOutOfMemory ? PIC_ERR_OOM : PIC_ERR_DEVICE, m);
+}
+
+#define HIP_TRY(ctx, expr, what)                 \
+  do {                                           \
+    hipError_t e_ = (expr);                      \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+  } while (0)
+
+template <typename T>
+pic_status dalloc(pic_ctx *c, T **p, size_t count, const char *what) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  void *q = nullptr;
+  hipError_t e = hipMalloc(&q, count * sizeof(T));
+  if (e != hipSuccess) return hip_fail(c, e, what);
+  *p = static_cast<T *>(q);
+  c->bytes += (int64_t)(count * sizeof(T));
+  return PIC_OK;
+}
+
+void dfree(pic_ctx *c, void *p, size_t bytes) {
+  if (p) {
+    (void)hipFree(p);
+    c->bytes -= (int64_t)bytes;
+  }
+}
+
+void free_species(pic_ctx *c, SpeciesState &s) {
+  const size_t cap = (size_t)std::max<int64_t>(s.cap, 1);
+  const size_t nc = (size_t)c->g.ncells;
+  for (int b = 0; b < 2; ++b) {
+    for (int v = 0; v < 5; ++v) dfree(c, s.buf[b][v], cap * sizeof(double)), s.buf[b][v] = nullptr;
+    dfree(c, s.ids[b], cap * sizeof(int64_t)), s.ids[b] = nullptr;
+    dfree(c, s.perm[b], cap * sizeof(int32_t)), s.perm[b] = nullptr;
+    dfree(c, s.cs[b], (nc + 1) * sizeof(int32_t)), s.cs[b] = nullptr;
+  }
+  dfree(c, s.code, cap), s.code = nullptr;
+  dfree(c, s.cnt, (size_t)pic::kMoveCodes * nc * sizeof(int32_t)), s.cnt = nullptr;
+  dfree(c, s.bsum, (size_t)c->n_scan_blocks * sizeof(int32_t)), s.bsum = nullptr;
+  s.loaded = false;
+  s.cap = 0;
+}
+
+bool finite3(const double *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+// Tile size from the load: about 2048 particles per tile, square, a power of two in [4, 16],
+// shrunk until the LDS accumulators fit in 64 KiB.
+void choose_tiles(pic_ctx *c, int64_t total, int64_t occupied) {
+  int tx = c->d.tile_x, tz = c->d.tile_z;
+  if (tx <= 0 || tz <= 0) {
+    double ppc = occupied > 0 ? (double)total / (double)occupied : 1.0;
+    int t = 4;
+    while (t < 16 && (double)(2 * t) * (2 * t) * ppc <= 2048.0 * 1.5) t *= 2;
+    tx = tz = t;
+    while (tx > 4 && pic::particle_lds_bytes(c->g, pic::TileArgs{tx, tz, 0, 0, 0, 0}) > 65536) {
+      tx /= 2;
+      tz /= 2;
+    }
+  }
+  c->tiles.tx = tx;
+  c->tiles.tz = tz;
+  c->tiles.ntx = (c->g.nx + tx - 1) / tx;
+  c->tiles.ntz = (c->g.nz + tz - 1) / tz;
+  c->tiles.ntiles = c->tiles.ntx * c->tiles.ntz;
+  c->tiles.per_xcd = (c->tiles.ntiles + 7) / 8;
+}
+
+pic::StepArgs step_args(pic_ctx *c, bool push) {
+  pic::StepArgs a{};
+  a.g = c->g;
+  a.t = c->tiles;
+  a.nsp = c->S;
+  const int cur = c->cur, nxt = 1 - c->cur;
+  for (int s = 0; s < c->S; ++s) {
+    SpeciesState &st = c->sp[s];
+    pic::SpeciesArgs &x = a.sp[s];
+    x.active = st.loaded ? 1 : 0;
+    if (!st.loaded) continue;
+    x.q = st.q;
+    x.m = st.m;
+    x.w = st.w;
+    x.beta = st.q * c->g.dt / (2.0 * st.m);
+    x.cS = st.w * st.q * st.q * c->g.dt * c->g.dt / (4.0 * st.m);
+    x.kJ = st.w * st.q;
+    for (int v = 0; v < 5; ++v) {
+      x.src[v] = st.buf[cur][v];
+      x.dst[v] = push ? st.buf[nxt][v] : nullptr;
+    }
+    x.src_id = st.ids[cur];
+    x.dst_id = push ? st.ids[nxt] : nullptr;
+    x.perm = st.perm[cur];
+    x.perm_new = st.perm[nxt];
+    x.cs = st.cs[cur];
+    x.cs_new = st.cs[nxt];
+    x.code = st.code;
+    x.cnt = st.cnt;
+    x.bsum = st.bsum;
+  }
+  a.flags = c->flags;
+  return a;
+}
+
+// Deposit M^{k+1/2} of the current state (used after loads).
+pic_status redeposit(pic_ctx *c) {
+  HIP_TRY(c, hipMemsetAsync(c->M, 0, (size_t)c->g.n_planes * c->g.nnodes * sizeof(double), c->stream),
+          "clear moments");
+  bool any = false;
+  for (int s = 0; s < c->S; ++s) any = any || c->sp[s].loaded;
+  if (!any) return PIC_OK;
+  pic::StepArgs a = step_args(c, false);
+  a.Ebar = c->Ebar;
+  a.Hold = c->H[c->hcur];
+  a.Hnew = c->H[c->hcur];
+  a.M = c->M;
+  HIP_TRY(c, pic::launch_particles(a, false, c->stream), "deposit kernel");
+  return PIC_OK;
+}
+
+void prof_accumulate(pic_ctx *c) {
+  for (size_t q = 0; q < c->prof_used; ++q) {
+    ProfEvents &p = c->prof_ev[q];
+    float t_field = 0, t_part = 0, t_sort = 0, t_step = 0;
+    (void)hipEventElapsedTime(&t_field, p.ev[0], p.ev[1]);
+    (void)hipEventElapsedTime(&t_part, p.ev[1], p.ev[2]);
+    (void)hipEventElapsedTime(&t_sort, p.ev[2], p.ev[3]);
+    (void)hipEventElapsedTime(&t_step, p.ev[0], p.ev[3]);
+    c->prof_acc.steps += 1;
+    c->prof_acc.field_launches += 1;
+    c->prof_acc.particle_launches += 1;
+    c->prof_acc.sort_launches += 1;
+    c->prof_acc.field_ms += t_field;
+    c->prof_acc.particle_ms += t_part;
+    c->prof_acc.sort_ms += t_sort;
+    c->prof_acc.step_ms += t_step;
+  }
+  c->prof_used = 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+pic_status pic_init_grid(const pic_grid_desc *d, pic_ctx **out) {
+  if (!out) return fail(nullptr, PIC_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!d) return fail(nullptr, PIC_ERR_ARG, "descriptor is NULL");
+  for (int r = 0; r < 7; ++r)
+    if (d->reserved[r] != 0) return fail(nullptr, PIC_ERR_ARG, "reserved fields must be zero");
+  if (d->nx < 1 || d->nz < 1) return fail(nullptr, PIC_ERR_ARG, "nx and nz must be >= 1");
+  if ((int64_t)d->nx * d->nz > 0x7fffffffLL - 1) return fail(nullptr, PIC_ERR_ARG, "too many cells");
+  if (!(d->dx > 0 && d->dz > 0 && d->dt > 0) || !std::isfinite(d->dx) || !std::isfinite(d->dz) ||
+      !std::isfinite(d->dt))
+    return fail(nullptr, PIC_ERR_ARG, "dx, dz, dt must be positive and finite");
+  if (d->bc_x != PIC_BC_PERIODIC && d->bc_x != PIC_BC_ABSORBING)
+    return fail(nullptr, PIC_ERR_ARG, "bc_x must be periodic or absorbing");
+  if (d->bc_z != PIC_BC_PERIODIC) return fail(nullptr, PIC_ERR_ARG, "bc_z must be periodic");
+  if (d->bc_x == PIC_BC_ABSORBING && d->nx < 2)
+    return fail(nullptr, PIC_ERR_ARG, "an absorbing x axis needs nx >= 2");
+  if (d->precision != PIC_PREC_FP64)
+    return fail(nullptr, PIC_ERR_ARG, "precision: only PIC_PREC_FP64 is available");
+  if (d->n_species < 1 || d->n_species > PIC_MAX_SPECIES)
+    return fail(nullptr, PIC_ERR_ARG, "n_species must be in 1..8");
+  if (d->allow_cfl_violation != 0 || d->dt > std::min(d->dx, d->dz))
+    return fail(nullptr, PIC_ERR_ARG,
+                "dt must not exceed min(dx, dz): the explicit curls are unstable beyond it and the "
+                "cell sort relies on particles moving less than one cell per cycle");
+  if (d->track_ids != 0 && d->track_ids != 1) return fail(nullptr, PIC_ERR_ARG, "track_ids must be 0 or 1");
+  if (d->tile_x < 0 || d->tile_z < 0 || d->tile_x > 64 || d->tile_z > 64 ||
+      ((d->tile_x == 0) != (d->tile_z == 0)))
+    return fail(nullptr, PIC_ERR_ARG, "tile_x, tile_z must both be 0 or both in 1..64");
+  if (!finite3(d->e0) || !finite3(d->h0)) return fail(nullptr, PIC_ERR_ARG, "e0, h0 must be finite");
+  const double lz[6] = {d->laser_a0, d->laser_omega, d->laser_sigma_z, d->laser_z_center,
+                        d->laser_fwhm_t, d->laser_t_center};
+  for (double v : lz)
+    if (!std::isfinite(v)) return fail(nullptr, PIC_ERR_ARG, "laser parameters must be finite");
+  if (d->laser_a0 != 0.0) {
+    if (d->bc_x != PIC_BC_ABSORBING)
+      return fail(nullptr, PIC_ERR_ARG, "the x = 0 source needs an absorbing x axis");
+    if (!(d->laser_sigma_z > 0 && d->laser_fwhm_t > 0))
+      return fail(nullptr, PIC_ERR_ARG, "laser sigma_z and fwhm_t must be positive");
+  }
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev < 1) return fail(nullptr, PIC_ERR_DEVICE, "no HIP device available");
+  if (d->device < 0 || d->device >= ndev) return fail(nullptr, PIC_ERR_ARG, "device ordinal out of range");
+  e = hipSetDevice(d->device);
+  if (e != hipSuccess) return fail(nullptr, PIC_ERR_DEVICE, "hipSetDevice failed");
+
+  pic_ctx *c = new pic_ctx();
+  c->d = *d;
+  c->S = d->n_species;
+  pic::GridArgs &g = c->g;
+  g.nx = d->nx;
+  g.nz = d->nz;
+  g.nxn = d->nx + (d->bc_x == PIC_BC_ABSORBING ? 1 : 0);
+  g.nzn = d->nz;
+  g.bc_x = d->bc_x;
+  g.n_planes = 12 + c->S;
+  g.ncells = (int64_t)d->nx * d->nz;
+  g.nnodes = (int64_t)g.nxn * g.nzn;
+  g.dx = d->dx;
+  g.dz = d->dz;
+  g.dt = d->dt;
+  g.cx = d->dt / d->dx;
+  g.cz = d->dt / d->dz;
+  c->laser = pic::LaserArgs{d->laser_a0, d->laser_omega, d->laser_sigma_z, d->laser_z_center,
+                            d->laser_fwhm_t, d->laser_t_center};
+  c->n_scan_blocks = (int32_t)((g.ncells + pic::kScanBlock - 1) / pic::kScanBlock);
+  choose_tiles(c, 0, 0);
+
+  pic_status st = PIC_OK;
+  auto bail = [&](pic_status s2) {
+    g_init_error = c->err;
+    pic_destroy(c);
+    return s2;
+  };
+  e = hipStreamCreate(&c->own_stream);
+  if (e != hipSuccess) return bail(hip_fail(c, e, "hipStreamCreate"));
+  c->stream = c->own_stream;
+  const size_t nn = (size_t)g.nnodes, nc = (size_t)g.ncells;
+  for (int b = 0; b < 2; ++b) {
+    if ((st = dalloc(c, &c->E[b], 3 * nn, "alloc E")) != PIC_OK) return bail(st);
+    if ((st = dalloc(c, &c->H[b], 3 * nc, "alloc H")) != PIC_OK) return bail(st);
+  }
+  if ((st = dalloc(c, &c->Ebar, 3 * nn, "alloc E-bar")) != PIC_OK) return bail(st);
+  if ((st = dalloc(c, &c->M, (size_t)g.n_planes * nn, "alloc moments")) != PIC_OK) return bail(st);
+  if ((st = dalloc(c, &c->flags, 1, "alloc flags")) != PIC_OK) return bail(st);
+  std::vector<double> host(3 * std::max(nn, nc));
+  for (int r = 0; r < 3; ++r) std::fill(host.begin() + r * nn, host.begin() + (r + 1) * nn, d->e0[r]);
+  e = hipMemcpy(c->E[0], host.data(), 3 * nn * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return bail(hip_fail(c, e, "upload E"));
+  e = hipMemcpy(c->Ebar, host.data(), 3 * nn * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return bail(hip_fail(c, e, "upload E-bar"));
+  for (int r = 0; r < 3; ++r) std::fill(host.begin() + r * nc, host.begin() + (r + 1) * nc, d->h0[r]);
+  e = hipMemcpy(c->H[0], host.data(), 3 * nc * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return bail(hip_fail(c, e, "upload H"));
+  e = hipMemset(c->M, 0, (size_t)g.n_planes * nn * sizeof(double));
+  if (e != hipSuccess) return bail(hip_fail(c, e, "clear moments"));
+  e = hipMemset(c->flags, 0, sizeof(uint32_t));
+  if (e != hipSuccess) return bail(hip_fail(c, e, "clear flags"));
+  *out = c;
+  return PIC_OK;
+}
+
+pic_status pic_load_particles(pic_ctx *c, int32_t s, double q, double m, double w, int64_t n,
+                              const double *xi_x, const double *xi_z, const double *ux,
+                              const double *uy, const double *uz) {
+  if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
+  if (s < 0 || s >= c->S) return fail(c, PIC_ERR_ARG, "species index out of range");
+  if (n < 0 || n > 0x7fffffffLL - 1) return fail(c, PIC_ERR_ARG, "n out of range");
+  if (!std::isfinite(q) || !std::isfinite(w) || !(m > 0) || !std::isfinite(m))
+    return fail(c, PIC_ERR_ARG, "q, w must be finite and m positive");
+  if (n > 0 && (!xi_x || !xi_z || !ux || !uy || !uz)) return fail(c, PIC_ERR_ARG, "NULL particle array");
+  const pic::GridArgs &g = c->g;
+  const int64_t nc = g.ncells;
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  // validate and sort by cell (stable counting sort; input order breaks ties)
+  std::vector<int32_t> key((size_t)n);
+  std::vector<int32_t> start((size_t)nc + 1, 0);
+  for (int64_t a = 0; a < n; ++a) {
+    const double x = xi_x[a], z = xi_z[a];
+    if (!(x >= 0.0 && x < (double)g.nx && z >= 0.0 && z < (double)g.nz))
+      return fail(c, PIC_ERR_RANGE, "particle " + std::to_string(a) + " lies outside the domain");
+    if (!std::isfinite(ux[a]) || !std::isfinite(uy[a]) || !std::isfinite(uz[a]))
+      return fail(c, PIC_ERR_RANGE, "particle " + std::to_string(a) + " has a non-finite momentum");
+    const int32_t i = (int32_t)std::floor(x), k = (int32_t)std::floor(z);
+    key[a] = k * g.nx + i;
+    start[(size_t)key[a] + 1] += 1;
+  }
+  for (int64_t cc = 0; cc < nc; ++cc) start[cc + 1] += start[cc];
+  std::vector<int32_t> order((size_t)n);
+  {
+    std::vector<int32_t> pos(start.begin(), start.end() - 1);
+    for (int64_t a = 0; a < n; ++a) order[pos[key[a]]++] = (int32_t)a;
+  }
+  SpeciesState &st = c->sp[s];
+  free_species(c, st);
+  st.q = q;
+  st.m = m;
+  st.w = w;
+  st.cap = n;
+  st.n_loaded = n;
+  const size_t cap = (size_t)std::max<int64_t>(n, 1);
+  pic_status rs;
+  for (int b = 0; b < 2; ++b) {
+    for (int v = 0; v < 5; ++v)
+      if ((rs = dalloc(c, &st.buf[b][v], cap, "alloc particles")) != PIC_OK) return rs;
+    if (c->d.track_ids)
+      if ((rs = dalloc(c, &st.ids[b], cap, "alloc ids")) != PIC_OK) return rs;
+    if ((rs = dalloc(c, &st.perm[b], cap, "alloc perm")) != PIC_OK) return rs;
+    if ((rs = dalloc(c, &st.cs[b], (size_t)nc + 1, "alloc cell starts")) != PIC_OK) return rs;
+  }
+  if ((rs = dalloc(c, &st.code, cap, "alloc codes")) != PIC_OK) return rs;
+  if ((rs = dalloc(c, &st.cnt, (size_t)pic::kMoveCodes * nc, "alloc counts")) != PIC_OK) return rs;
+  if ((rs = dalloc(c, &st.bsum, (size_t)c->n_scan_blocks, "alloc scan sums")) != PIC_OK) return rs;
+  {
+    std::vector<double> tmp((size_t)n);
+    const double *srcs[5] = {xi_x, xi_z, ux, uy, uz};
+    for (int v = 0; v < 5; ++v) {
+      for (int64_t j = 0; j < n; ++j) tmp[j] = srcs[v][order[j]];
+      HIP_TRY(c, hipMemcpy(st.buf[c->cur][v], tmp.data(), (size_t)n * sizeof(double), hipMemcpyHostToDevice),
+              "upload particles");
+    }
+    if (c->d.track_ids) {
+      std::vector<int64_t> idv((size_t)n);
+      for (int64_t j = 0; j < n; ++j) idv[j] = order[j];
+      HIP_TRY(c, hipMemcpy(st.ids[c->cur], idv.data(), (size_t)n * sizeof(int64_t), hipMemcpyHostToDevice),
+              "upload ids");
+    }
+  }
+  HIP_TRY(c, hipMemcpy(st.cs[c->cur], start.data(), ((size_t)nc + 1) * sizeof(int32_t), hipMemcpyHostToDevice),
+          "upload cell starts");
+  HIP_TRY(c, pic::launch_iota(st.perm[c->cur], n, c->stream), "identity permutation");
+  st.loaded = true;
+  // tiles from all loaded species
+  {
+    std::vector<uint8_t> occ((size_t)nc, 0);
+    int64_t total = 0;
+    for (int ss = 0; ss < c->S; ++ss) {
+      if (!c->sp[ss].loaded) continue;
+      std::vector<int32_t> csh((size_t)nc + 1);
+      if (ss == s) {
+        csh = start;
+      } else {
+        HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+        HIP_TRY(c, hipMemcpy(csh.data(), c->sp[ss].cs[c->cur], ((size_t)nc + 1) * sizeof(int32_t),
+                             hipMemcpyDeviceToHost), "read cell starts");
+      }
+      for (int64_t cc = 0; cc < nc; ++cc)
+        if (csh[cc + 1] > csh[cc]) occ[cc] = 1;
+      total += csh[nc];
+    }
+    int64_t occupied = 0;
+    for (uint8_t o : occ) occupied += o;
+    choose_tiles(c, total, occupied);
+    if (pic::particle_lds_bytes(c->g, c->tiles) > 65536)
+      return fail(c, PIC_ERR_ARG, "tile too large: its LDS accumulators exceed 64 KiB");
+  }
+  HIP_TRY(c, hipMemsetAsync(c->flags, 0, sizeof(uint32_t), c->stream), "clear flags");
+  return redeposit(c);
+}
+
+pic_status pic_load_fields(pic_ctx *c, const double *e, const double *h) {
+  if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
+  const size_t nn = (size_t)c->g.nnodes, nc = (size_t)c->g.ncells;
+  if (e)
+    for (size_t q = 0; q < 3 * nn; ++q)
+      if (!std::isfinite(e[q])) return fail(c, PIC_ERR_RANGE, "non-finite E");
+  if (h)
+    for (size_t q = 0; q < 3 * nc; ++q)
+      if (!std::isfinite(h[q])) return fail(c, PIC_ERR_RANGE, "non-finite H");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  if (e) HIP_TRY(c, hipMemcpy(c->E[c->ecur], e, 3 * nn * sizeof(double), hipMemcpyHostToDevice), "upload E");
+  if (h) HIP_TRY(c, hipMemcpy(c->H[c->hcur], h, 3 * nc * sizeof(double), hipMemcpyHostToDevice), "upload H");
+  HIP_TRY(c, hipMemsetAsync(c->flags, 0, sizeof(uint32_t), c->stream), "clear flags");
+  return redeposit(c);
+}
+
+pic_status pic_set_step(pic_ctx *c, int64_t step) {
+  if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
+  if (step < 0) return fail(c, PIC_ERR_ARG, "step must be >= 0");
+  c->step = step;
+  return PIC_OK;
+}
+
+pic_status pic_step(pic_ctx *c, int32_t nsteps) {
+  if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
+  if (nsteps < 0) return fail(c, PIC_ERR_ARG, "nsteps must be >= 0");
+  bool any = false;
+  for (int s = 0; s < c->S; ++s) any = any || c->sp[s].loaded;
+  if (!any) return fail(c, PIC_ERR_STATE, "no particles loaded");
+  for (int32_t it = 0; it < nsteps; ++it) {
+    ProfEvents *pe = nullptr;
+    if (c->prof_on) {
+      if (c->prof_used == c->prof_ev.size()) {
+        if (c->prof_ev.size() >= 4096) {
+          HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+          prof_accumulate(c);
+        } else {
+          ProfEvents p{};
+          for (int q = 0; q < 4; ++q) HIP_TRY(c, hipEventCreate(&p.ev[q]), "event create");
+          c->prof_ev.push_back(p);
+        }
+      }
+      pe = &c->prof_ev[c->prof_used++];
+      HIP_TRY(c, hipEventRecord(pe->ev[0], c->stream), "event record");
+    }
+    pic::FieldArgs fa{};
+    fa.g = c->g;
+    fa.laser = c->laser;
+    fa.t = (double)c->step * c->g.dt;
+    fa.M = c->M;
+    fa.E = c->E[c->ecur];
+    fa.H = c->H[c->hcur];
+    fa.E_new = c->E[1 - c->ecur];
+    fa.Ebar = c->Ebar;
+    fa.H_new = c->H[1 - c->hcur];
+    fa.M_clear = c->M;
+    HIP_TRY(c, pic::launch_field_solve(fa, c->stream), "field solve");
+    if (pe) HIP_TRY(c, hipEventRecord(pe->ev[1], c->stream), "event record");
+    pic::StepArgs a = step_args(c, true);
+    a.Ebar = c->Ebar;
+    a.Hold = c->H[c->hcur];
+    a.Hnew = c->H[1 - c->hcur];
+    a.M = c->M;
+    HIP_TRY(c, pic::launch_particles(a, true, c->stream), "particle kernel");
+    if (pe) HIP_TRY(c, hipEventRecord(pe->ev[2], c->stream), "event record");
+    HIP_TRY(c, pic::launch_sort(a, c->n_scan_blocks, c->stream), "sort kernels");
+    if (pe) HIP_TRY(c, hipEventRecord(pe->ev[3], c->stream), "event record");
+    c->ecur ^= 1;
+    c->hcur ^= 1;
+    c->cur ^= 1;
+    c->step += 1;
+  }
+  return PIC_OK;
+}
+
+pic_status pic_read_moments(pic_ctx *c, double *out, int64_t len) {
+  if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
+  const int64_t need = (int64_t)c->g.n_planes * c->g.nnodes;
+  if (!out || len < need) return fail(c, PIC_ERR_ARG, "output buffer too small");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  HIP_TRY(c, hipMemcpy(out, c->M, (size_t)need * sizeof(double), hipMemcpyDeviceToHost), "read moments");
+  return PIC_OK;
+}
+
+pic_status pic_read_fields(pic_ctx *c, double *e, double *h) {
+  if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  if (e) HIP_TRY(c, hipMemcpy(e, c->E[c->ecur], 3 * (size_t)c->g.nnodes * sizeof(double), hipMemcpyDeviceToHost), "read E");
+  if (h) HIP_TRY(c, hipMemcpy(h, c->H[c->hcur], 3 * (size_t)c->g.ncells * sizeof(double), hipMemcpyDeviceToHost), "read H");
+  return PIC_OK;
+}
+
+static pic_status alive_count(pic_ctx *c, int s, int64_t *n) {
+  *n = 0;
+  if (!c->sp[s].loaded) return PIC_OK;
+  int32_t v = 0;
+  HIP_TRY(c, hipMemcpy(&v, c->sp[s].cs[c->cur] + c->g.ncells, sizeof(int32_t), hipMemcpyDeviceToHost),
+          "read count");
+  *n = v;
+  return PIC_OK;
+}
+
+pic_status pic_read_particles(pic_ctx *c, int32_t s, int64_t *n_inout, double *xi_x, double *xi_z,
+                              double *ux, double *uy, double *uz, int64_t *id) {
+  if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
+  if (s < 0 || s >= c->S || !n_inout) return fail(c, PIC_ERR_ARG, "bad species or n_inout");
+  if (id && !c->d.track_ids) return fail(c, PIC_ERR_ARG, "ids need track_ids");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  int64_t n = 0;
+  pic_status rs = alive_count(c, s, &n);
+  if (rs != PIC_OK) return rs;
+  if (*n_inout < n) {
+    *n_inout = n;
+    return fail(c, PIC_ERR_ARG, "particle arrays too small");
+  }
+  *n_inout = n;
+  if (n == 0) return PIC_OK;
+  SpeciesState &st = c->sp[s];
+  std::vector<int32_t> perm((size_t)n);
+  HIP_TRY(c, hipMemcpy(perm.data(), st.perm[c->cur], (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost),
+          "read perm");
+  std::vector<double> tmp((size_t)st.cap);
+  double *outs[5] = {xi_x, xi_z, ux, uy, uz};
+  for (int v = 0; v < 5; ++v) {
+    if (!outs[v]) continue;
+    HIP_TRY(c, hipMemcpy(tmp.data(), st.buf[c->cur][v], (size_t)st.cap * sizeof(double), hipMemcpyDeviceToHost),
+            "read particles");
+    for (int64_t j = 0; j < n; ++j) outs[v][j] = tmp[perm[j]];
+  }
+  if (id) {
+    std::vector<int64_t> t2((size_t)st.cap);
+    HIP_TRY(c, hipMemcpy(t2.data(), st.ids[c->cur], (size_t)st.cap * sizeof(int64_t), hipMemcpyDeviceToHost),
+            "read ids");
+    for (int64_t j = 0; j < n; ++j) id[j] = t2[perm[j]];
+  }
+  return PIC_OK;
+}
+
+pic_status pic_get_info(pic_ctx *c, pic_info *info) {
+  if (!c || !info) return fail(c, PIC_ERR_ARG, "NULL argument");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  pic_info r{};
+  r.step = c->step;
+  r.t = (double)c->step * c->g.dt;
+  r.n_species = c->S;
+  r.nodes_x = c->g.nxn;
+  r.nodes_z = c->g.nzn;
+  r.cells_x = c->g.nx;
+  r.cells_z = c->g.nz;
+  r.tile_x = c->tiles.tx;
+  r.tile_z = c->tiles.tz;
+  r.precision = c->d.precision;
+  for (int s = 0; s < c->S; ++s) {
+    int64_t n = 0;
+    pic_status rs = alive_count(c, s, &n);
+    if (rs != PIC_OK) return rs;
+    r.alive[s] = n;
+    r.absorbed[s] = c->sp[s].loaded ? c->sp[s].n_loaded - n : 0;
+  }
+  HIP_TRY(c, hipMemcpy(&r.overflow_flags, c->flags, sizeof(uint32_t), hipMemcpyDeviceToHost), "read flags");
+  r.device_bytes = c->bytes;
+  *info = r;
+  return PIC_OK;
+}
+
+pic_status pic_set_stream(pic_ctx *c, void *stream) {
+  if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  c->stream = stream ? static_cast<hipStream_t>(stream) : c->own_stream;
+  return PIC_OK;
+}
+
+pic_status pic_sync(pic_ctx *c) {
+  if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  return PIC_OK;
+}
+
+pic_status pic_profile_enable(pic_ctx *c, int32_t on) {
+  if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  if (on) {
+    c->prof_used = 0;
+    c->prof_acc = pic_profile{};
+    c->prof_on = true;
+  } else {
+    prof_accumulate(c);
+    c->prof_on = false;
+  }
+  return PIC_OK;
+}
+
+pic_status pic_profile_read(pic_ctx *c, pic_profile *out) {
+  if (!c || !out) return fail(c, PIC_ERR_ARG, "NULL argument");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  prof_accumulate(c);
+  *out = c->prof_acc;
+  return PIC_OK;
+}
+
+const char *pic_last_error(const pic_ctx *c) { return c ? c->err.c_str() : g_init_error.c_str(); }
+
+void pic_destroy(pic_ctx *c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (int s = 0; s < PIC_MAX_SPECIES; ++s) free_species(c, c->sp[s]);
+  const size_t nn = (size_t)c->g.nnodes, nc = (size_t)c->g.ncells;
+  for (int b = 0; b < 2; ++b) {
+    dfree(c, c->E[b], 3 * nn * sizeof(double));
+    dfree(c, c->H[b], 3 * nc * sizeof(double));
+  }
+  dfree(c, c->Ebar, 3 * nn * sizeof(double));
+  dfree(c, c->M, (size_t)c->g.n_planes * nn * sizeof(double));
+  dfree(c, c->flags, sizeof(uint32_t));
+  for (auto &p : c->prof_ev)
+    for (int q = 0; q < 4; ++q) (void)hipEventDestroy(p.ev[q]);
+  if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,89 @@
+// Internal interface between the host side of the library (pic_capi.cpp) and the HIP
+// kernels (pic_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pic.h"
+
+namespace pic {
+
+constexpr int kMaxSpecies = PIC_MAX_SPECIES;
+constexpr int kMoveCodes = 9;      // destination cell relative to the source: 3 x 3 block
+constexpr uint8_t kAbsorbed = 9;   // move code of a particle that left an absorbing boundary
+constexpr int kBlock = 256;        // threads per block of the tile kernels (4 wavefronts)
+constexpr int kScanItems = 4;      // cells per thread in the count scan
+constexpr int kScanBlock = kBlock * kScanItems;
+
+struct GridArgs {
+  int32_t nx, nz, nxn, nzn;  // cells and nodes per axis
+  int32_t bc_x;              // PIC_BC_PERIODIC or PIC_BC_ABSORBING (z is periodic)
+  int32_t n_planes;          // 12 + S moment planes
+  int64_t ncells, nnodes;
+  double dx, dz, dt;
+  double cx, cz;             // dt / dx, dt / dz
+};
+
+struct LaserArgs {
+  double a0, omega, sigma_z, z_center, fwhm_t, t_center;
+};
+
+struct TileArgs {
+  int32_t tx, tz;            // cells per tile
+  int32_t ntx, ntz, ntiles;  // tiles per axis and in total
+  int32_t per_xcd;           // tiles per XCD band: launch grid is 8 * per_xcd blocks
+};
+
+// FP64 particle state: structure of arrays, 5 planes (xi_x, xi_z, u_x, u_y, u_z).
+struct SpeciesArgs {
+  double q, m, w;
+  double beta;               // q dt / (2 m)
+  double cS;                 // w q^2 dt^2 / (4 m)
+  double kJ;                 // w q
+  const double *src[5];      // current state, addressed through perm
+  double *dst[5];            // pushed state, written in sorted-slot order
+  const int64_t *src_id;
+  int64_t *dst_id;
+  const int32_t *perm;       // sorted slot -> location in src
+  int32_t *perm_new;         // next cycle's sorted slot -> location in dst
+  const int32_t *cs;         // cell start offsets of the current order [ncells + 1]
+  int32_t *cs_new;           // cell start offsets of the next order [ncells + 1]
+  uint8_t *code;             // move code per sorted slot
+  int32_t *cnt;              // [9][ncells] particles leaving each cell per move code
+  int32_t *bsum;             // block sums of the count scan
+  int32_t active;
+};
+
+struct StepArgs {
+  GridArgs g;
+  TileArgs t;
+  int32_t nsp;               // species slots
+  SpeciesArgs sp[kMaxSpecies];
+  const double *Ebar;        // [3][nodes]
+  const double *Hold;        // H^{n+1/2} [3][cells]
+  const double *Hnew;        // H^{n+3/2} [3][cells]
+  double *M;                 // moment planes [12 + S][nodes]
+  uint32_t *flags;
+};
+
+struct FieldArgs {
+  GridArgs g;
+  LaserArgs laser;
+  double t;                  // time of E^n
+  const double *M;
+  const double *E;           // E^n
+  const double *H;           // H^{n+1/2}
+  double *E_new, *Ebar, *H_new;
+  double *M_clear;           // moment planes zeroed by the H update (NULL: keep)
+};
+
+size_t particle_lds_bytes(const GridArgs &g, const TileArgs &t);
+size_t rank_lds_bytes(const TileArgs &t);
+
+hipError_t launch_field_solve(const FieldArgs &a, hipStream_t s);
+hipError_t launch_particles(const StepArgs &a, bool push, hipStream_t s);
+hipError_t launch_sort(const StepArgs &a, int32_t n_scan_blocks, hipStream_t s);
+hipError_t launch_iota(int32_t *p, int64_t n, hipStream_t s);
+
+}  // namespace pic
