@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget for the CPU oracle baseline (0 disables it)")
     ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB before the timed region "
+                         "(reference dispatch for scaling HBM byte counters)")
     return ap.parse_args()
 
 
@@ -81,6 +84,14 @@ def main():
         sys.exit(2)
     import torch
     from paper_1308_2590_amd import binding
+
+    if args.calibrate_copy_mib > 0:
+        n = args.calibrate_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     wl = picgen.named(args.workload)
     S = wl.grid.n_species

@@ -241,7 +241,8 @@ def test_edge_cases(pic):
         check_particles(ctx, orc, wl)
     info = ctx.get_info()
     assert info["alive"][0] == 0 and info["alive"][1] == 0 and info["absorbed"][1] == 4
-    assert info["alive"][2] == 6 and info["overflow_flags"] == 0
+    assert info["alive"] == [orc.species[s].n for s in range(3)]
+    assert info["absorbed"] == orc.absorbed and info["overflow_flags"] == 0
     ctx.close()
 
 
