@@ -119,7 +119,7 @@ pic_status pic_init_grid(const pic_grid_desc *desc, pic_ctx **out);
  * breaks ties), and the moments M^{k+1/2} of all species are deposited again.  When
  * track_ids is set, particle a gets label a.  Errors: PIC_ERR_ARG (s out of range, n < 0,
  * m <= 0, q or w not finite, NULL array with n > 0), PIC_ERR_RANGE (a position outside
- * [0, nx) x [0, nz) or a non-finite value), PIC_ERR_OOM. */
+ * [0, nx) x [0, nz) or a non-finite value), PIC_ERR_OOM.  At most 2^28 - 1 particles per species. */
 pic_status pic_load_particles(pic_ctx *ctx, int32_t species, double q, double m, double w,
                               int64_t n, const double *xi_x, const double *xi_z,
                               const double *ux, const double *uy, const double *uz);

@@ -25,7 +25,7 @@ struct SpeciesState {
   int64_t *ids[2] = {};
   int32_t *perm[2] = {};
   int32_t *cs[2] = {};     // cell start offsets [ncells + 1]
-  uint8_t *code = nullptr;
+  uint32_t *locode = nullptr;
   int32_t *cnt = nullptr;  // [9][ncells]
   int32_t *bsum = nullptr;
 };
@@ -48,6 +48,10 @@ struct pic_ctx {
   int ecur = 0, hcur = 0, cur = 0;
   SpeciesState sp[PIC_MAX_SPECIES];
   uint32_t *flags = nullptr;
+  uint8_t *tact[2] = {};   // active-tile flags of the current / next order
+  int32_t *tlist[2] = {};  // ordered active-tile lists, count at [ntiles]
+  int32_t tiles_alloc = 0, tiles_tx = 0, tiles_tz = 0;
+  int32_t *col_tile = nullptr, *row_tile = nullptr;  // cell column / row -> tile index
   int64_t step = 0;
   int64_t bytes = 0;
   int32_t n_scan_blocks = 0;
@@ -108,7 +112,7 @@ void free_species(pic_ctx *c, SpeciesState &s) {
     dfree(c, s.perm[b], cap * sizeof(int32_t)), s.perm[b] = nullptr;
     dfree(c, s.cs[b], (nc + 1) * sizeof(int32_t)), s.cs[b] = nullptr;
   }
-  dfree(c, s.code, cap), s.code = nullptr;
+  dfree(c, s.locode, cap * sizeof(uint32_t)), s.locode = nullptr;
   dfree(c, s.cnt, (size_t)pic::kMoveCodes * nc * sizeof(int32_t)), s.cnt = nullptr;
   dfree(c, s.bsum, (size_t)c->n_scan_blocks * sizeof(int32_t)), s.bsum = nullptr;
   s.loaded = false;
@@ -117,19 +121,18 @@ void free_species(pic_ctx *c, SpeciesState &s) {
 
 bool finite3(const double *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
 
-// Tile size from the load: about 2048 particles per tile, square, a power of two in [4, 16],
-// shrunk until the LDS accumulators fit in 64 KiB.
-void choose_tiles(pic_ctx *c, int64_t total, int64_t occupied) {
+// Tile size from the load.  One wavefront handles one row of a tile, each lane a contiguous
+// run of that row's particles, so a tile is 4 rows high and wide enough for a row to hold
+// about 1024 particles of a species (runs of ~16); a power of two in [4, 32], shrunk until
+// the LDS accumulators fit in 64 KiB.
+void choose_tiles(pic_ctx *c, int64_t total, int64_t occupied, int nspecies) {
   int tx = c->d.tile_x, tz = c->d.tile_z;
   if (tx <= 0 || tz <= 0) {
-    double ppc = occupied > 0 ? (double)total / (double)occupied : 1.0;
-    int t = 4;
-    while (t < 16 && (double)(2 * t) * (2 * t) * ppc <= 2048.0 * 1.5) t *= 2;
-    tx = tz = t;
-    while (tx > 4 && pic::particle_lds_bytes(c->g, pic::TileArgs{tx, tz, 0, 0, 0, 0}) > 65536) {
-      tx /= 2;
-      tz /= 2;
-    }
+    double ppc = occupied > 0 ? (double)total / (double)occupied / std::max(nspecies, 1) : 1.0;
+    tx = 4;
+    while (tx < 32 && (double)(2 * tx) * ppc <= 1024.0 * 1.4) tx *= 2;
+    tz = 4;
+    while (tx > 4 && pic::particle_lds_bytes(c->g, pic::TileArgs{tx, tz, 0, 0, 0, 0}) > 65536) tx /= 2;
   }
   c->tiles.tx = tx;
   c->tiles.tz = tz;
@@ -166,12 +169,58 @@ pic::StepArgs step_args(pic_ctx *c, bool push) {
     x.perm_new = st.perm[nxt];
     x.cs = st.cs[cur];
     x.cs_new = st.cs[nxt];
-    x.code = st.code;
+    x.locode = st.locode;
     x.cnt = st.cnt;
     x.bsum = st.bsum;
   }
   a.flags = c->flags;
+  a.tile_active = c->tact[cur];
+  a.tile_list = c->tlist[cur];
+  a.tile_active_next = c->tact[nxt];
+  a.tile_list_next = c->tlist[nxt];
+  a.col_tile = c->col_tile;
+  a.row_tile = c->row_tile;
   return a;
+}
+
+// (Re)allocate the active-tile arrays for the current tile decomposition.
+pic_status alloc_tiles(pic_ctx *c) {
+  const int32_t nt = c->tiles.ntiles;
+  if (nt == c->tiles_alloc && c->tiles.tx == c->tiles_tx && c->tiles.tz == c->tiles_tz) return PIC_OK;
+  c->tiles_tx = c->tiles.tx;
+  c->tiles_tz = c->tiles.tz;
+  for (int b = 0; b < 2; ++b) {
+    dfree(c, c->tact[b], (size_t)std::max(c->tiles_alloc, 1));
+    dfree(c, c->tlist[b], ((size_t)c->tiles_alloc + 1) * sizeof(int32_t));
+    c->tact[b] = nullptr;
+    c->tlist[b] = nullptr;
+  }
+  c->tiles_alloc = 0;
+  pic_status st;
+  for (int b = 0; b < 2; ++b) {
+    if ((st = dalloc(c, &c->tact[b], (size_t)nt, "alloc tile flags")) != PIC_OK) return st;
+    if ((st = dalloc(c, &c->tlist[b], (size_t)nt + 1, "alloc tile list")) != PIC_OK) return st;
+  }
+  c->tiles_alloc = nt;
+  if (!c->col_tile) {
+    if ((st = dalloc(c, &c->col_tile, (size_t)c->g.nx, "alloc tile map")) != PIC_OK) return st;
+    if ((st = dalloc(c, &c->row_tile, (size_t)c->g.nz, "alloc tile map")) != PIC_OK) return st;
+  }
+  std::vector<int32_t> m((size_t)std::max(c->g.nx, c->g.nz));
+  for (int i = 0; i < c->g.nx; ++i) m[i] = i / c->tiles.tx;
+  HIP_TRY(c, hipMemcpy(c->col_tile, m.data(), (size_t)c->g.nx * sizeof(int32_t), hipMemcpyHostToDevice), "tile map");
+  for (int k = 0; k < c->g.nz; ++k) m[k] = k / c->tiles.tz;
+  HIP_TRY(c, hipMemcpy(c->row_tile, m.data(), (size_t)c->g.nz * sizeof(int32_t), hipMemcpyHostToDevice), "tile map");
+  return PIC_OK;
+}
+
+// Active-tile flags and list of the current order (after loads).
+pic_status build_tile_list(pic_ctx *c) {
+  pic::StepArgs a = step_args(c, false);
+  a.tile_active_next = c->tact[c->cur];
+  a.tile_list_next = c->tlist[c->cur];
+  HIP_TRY(c, pic::launch_tile_list(a, false, c->stream), "tile list");
+  return PIC_OK;
 }
 
 // Deposit M^{k+1/2} of the current state (used after loads).
@@ -181,6 +230,9 @@ pic_status redeposit(pic_ctx *c) {
   bool any = false;
   for (int s = 0; s < c->S; ++s) any = any || c->sp[s].loaded;
   if (!any) return PIC_OK;
+  pic_status rs = alloc_tiles(c);
+  if (rs != PIC_OK) return rs;
+  if ((rs = build_tile_list(c)) != PIC_OK) return rs;
   pic::StepArgs a = step_args(c, false);
   a.Ebar = c->Ebar;
   a.Hold = c->H[c->hcur];
@@ -280,7 +332,7 @@ pic_status pic_init_grid(const pic_grid_desc *d, pic_ctx **out) {
   c->laser = pic::LaserArgs{d->laser_a0, d->laser_omega, d->laser_sigma_z, d->laser_z_center,
                             d->laser_fwhm_t, d->laser_t_center};
   c->n_scan_blocks = (int32_t)((g.ncells + pic::kScanBlock - 1) / pic::kScanBlock);
-  choose_tiles(c, 0, 0);
+  choose_tiles(c, 0, 0, 1);
 
   pic_status st = PIC_OK;
   auto bail = [&](pic_status s2) {
@@ -321,7 +373,7 @@ pic_status pic_load_particles(pic_ctx *c, int32_t s, double q, double m, double 
                               const double *uy, const double *uz) {
   if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
   if (s < 0 || s >= c->S) return fail(c, PIC_ERR_ARG, "species index out of range");
-  if (n < 0 || n > 0x7fffffffLL - 1) return fail(c, PIC_ERR_ARG, "n out of range");
+  if (n < 0 || n >= (1LL << 28)) return fail(c, PIC_ERR_ARG, "n out of range (at most 2^28 - 1 per species)");
   if (!std::isfinite(q) || !std::isfinite(w) || !(m > 0) || !std::isfinite(m))
     return fail(c, PIC_ERR_ARG, "q, w must be finite and m positive");
   if (n > 0 && (!xi_x || !xi_z || !ux || !uy || !uz)) return fail(c, PIC_ERR_ARG, "NULL particle array");
@@ -364,7 +416,7 @@ pic_status pic_load_particles(pic_ctx *c, int32_t s, double q, double m, double 
     if ((rs = dalloc(c, &st.perm[b], cap, "alloc perm")) != PIC_OK) return rs;
     if ((rs = dalloc(c, &st.cs[b], (size_t)nc + 1, "alloc cell starts")) != PIC_OK) return rs;
   }
-  if ((rs = dalloc(c, &st.code, cap, "alloc codes")) != PIC_OK) return rs;
+  if ((rs = dalloc(c, &st.locode, cap, "alloc codes")) != PIC_OK) return rs;
   if ((rs = dalloc(c, &st.cnt, (size_t)pic::kMoveCodes * nc, "alloc counts")) != PIC_OK) return rs;
   if ((rs = dalloc(c, &st.bsum, (size_t)c->n_scan_blocks, "alloc scan sums")) != PIC_OK) return rs;
   {
@@ -406,7 +458,9 @@ pic_status pic_load_particles(pic_ctx *c, int32_t s, double q, double m, double 
     }
     int64_t occupied = 0;
     for (uint8_t o : occ) occupied += o;
-    choose_tiles(c, total, occupied);
+    int nloaded = 0;
+    for (int ss = 0; ss < c->S; ++ss) nloaded += c->sp[ss].loaded ? 1 : 0;
+    choose_tiles(c, total, occupied, nloaded);
     if (pic::particle_lds_bytes(c->g, c->tiles) > 65536)
       return fail(c, PIC_ERR_ARG, "tile too large: its LDS accumulators exceed 64 KiB");
   }
@@ -628,6 +682,12 @@ void pic_destroy(pic_ctx *c) {
   dfree(c, c->Ebar, 3 * nn * sizeof(double));
   dfree(c, c->M, (size_t)c->g.n_planes * nn * sizeof(double));
   dfree(c, c->flags, sizeof(uint32_t));
+  for (int b = 0; b < 2; ++b) {
+    dfree(c, c->tact[b], (size_t)std::max(c->tiles_alloc, 1));
+    dfree(c, c->tlist[b], ((size_t)c->tiles_alloc + 1) * sizeof(int32_t));
+  }
+  dfree(c, c->col_tile, (size_t)c->g.nx * sizeof(int32_t));
+  dfree(c, c->row_tile, (size_t)c->g.nz * sizeof(int32_t));
   for (auto &p : c->prof_ev)
     for (int q = 0; q < 4; ++q) (void)hipEventDestroy(p.ev[q]);
   if (c->own_stream) (void)hipStreamDestroy(c->own_stream);

@@ -42,14 +42,14 @@ struct SpeciesArgs {
   double cS;                 // w q^2 dt^2 / (4 m)
   double kJ;                 // w q
   const double *src[5];      // current state, addressed through perm
-  double *dst[5];            // pushed state, written in sorted-slot order
+  double *dst[5];            // pushed state, written in the kernel's processing order
   const int64_t *src_id;
   int64_t *dst_id;
   const int32_t *perm;       // sorted slot -> location in src
   int32_t *perm_new;         // next cycle's sorted slot -> location in dst
   const int32_t *cs;         // cell start offsets of the current order [ncells + 1]
   int32_t *cs_new;           // cell start offsets of the next order [ncells + 1]
-  uint8_t *code;             // move code per sorted slot
+  uint32_t *locode;          // per sorted slot: (location written << 4) | move code
   int32_t *cnt;              // [9][ncells] particles leaving each cell per move code
   int32_t *bsum;             // block sums of the count scan
   int32_t active;
@@ -65,6 +65,14 @@ struct StepArgs {
   const double *Hnew;        // H^{n+3/2} [3][cells]
   double *M;                 // moment planes [12 + S][nodes]
   uint32_t *flags;
+  // tiles holding particles of the current order (flag per tile; ordered list, count at
+  // [ntiles]) and the same for the next order, built after the count scan
+  const uint8_t *tile_active;
+  const int32_t *tile_list;
+  uint8_t *tile_active_next;
+  int32_t *tile_list_next;
+  const int32_t *col_tile;   // [nx]: tile column of each cell column
+  const int32_t *row_tile;   // [nz]: tile row of each cell row
 };
 
 struct FieldArgs {
@@ -85,5 +93,8 @@ hipError_t launch_field_solve(const FieldArgs &a, hipStream_t s);
 hipError_t launch_particles(const StepArgs &a, bool push, hipStream_t s);
 hipError_t launch_sort(const StepArgs &a, int32_t n_scan_blocks, hipStream_t s);
 hipError_t launch_iota(int32_t *p, int64_t n, hipStream_t s);
+// Build the active-tile flags and list of the order described by sp[].cs (into
+// tile_active_next / tile_list_next).
+hipError_t launch_tile_list(const StepArgs &a, bool from_next_order, hipStream_t s);
 
 }  // namespace pic

@@ -46,11 +46,16 @@ __device__ __forceinline__ int wrap_any(int i, int n) {
   return i < 0 ? i + n : i;
 }
 
-// The tile handled by this block: blocks are dealt round-robin to the 8 XCDs, so hand each
-// XCD a contiguous band of tiles (neighbouring tiles share halo nodes and field cache lines).
-__device__ __forceinline__ int block_tile(const TileArgs &t) {
-  int b = blockIdx.x;
-  return (b & 7) * t.per_xcd + (b >> 3);
+// The tile handled by this block, taken from the ordered list of tiles that hold particles:
+// blocks are dealt round-robin to the 8 XCDs, so each XCD gets a contiguous band of the list
+// (neighbouring tiles share halo nodes and field cache lines).  Surplus blocks return.
+__device__ __forceinline__ int block_tile(const TileArgs &t, const int32_t *list) {
+  const int count = list[t.ntiles];
+  const int per = (count + 7) >> 3;
+  const int b = blockIdx.x;
+  if ((b >> 3) >= per) return -1;
+  const int idx = (b & 7) * per + (b >> 3);
+  return idx < count ? list[idx] : -1;
 }
 
 // Implicit response of a particle: R = (I + [b]x + b b^T) / (1 + b.b) with b = (beta/gamma) B,
@@ -206,58 +211,222 @@ __global__ __launch_bounds__(kBlock) void k_update_h(const FieldArgs a) {
 // Particles
 // ------------------------------------------------------------------------------------------
 
-// Add the 12 implicit moments and the density of one particle, spread by the four linear
-// weights of its cell, to the tile's LDS accumulators (corner (lx, lz) is the cell's lower
-// left node in tile-local coordinates).
-__device__ __forceinline__ void deposit_lds(double *acc, int plane, int LW, int lx, int lz,
-                                            double fx, double fz, const double val[12],
-                                            int dens_plane, double w) {
-  const double W[4] = {(1.0 - fx) * (1.0 - fz), fx * (1.0 - fz), (1.0 - fx) * fz, fx * fz};
-  const int b = lz * LW + lx;
-  const int o[4] = {b, b + 1, b + LW, b + LW + 1};
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Compact moments of one particle in the field B of its cell.  With s = beta / gamma and
+// b = s B, R = (I + s [B]x + s^2 B B^T) / (1 + s^2 B.B), so
+//   S-hat = a0 I + a1 [B]x + a2 B B^T,  a0 = w q^2 dt^2 / (4 m gamma (1 + s^2 B.B)),
+//   a1 = a0 s, a2 = a1 s,
+//   delta-j = (w q / gamma) R u = (w q / (gamma (1 + s^2 B.B))) (u + s u x B + s^2 (B.u) B).
+// Particles sharing a cell share B, so their S-hat deposits add up through three scalars.
+struct Compact {
+  double a0, a1, a2, j0, j1, j2;
+};
+
+__device__ __forceinline__ Compact compact_moments(const SpeciesArgs &sp, double g, double u0,
+                                                   double u1, double u2, double B0, double B1,
+                                                   double B2) {
+  const double ginv = 1.0 / g;
+  const double s = sp.beta * ginv;
+  const double BB = B0 * B0 + B1 * B1 + B2 * B2;
+  const double inv = 1.0 / fma(s * s, BB, 1.0);
+  Compact m;
+  m.a0 = sp.cS * ginv * inv;
+  m.a1 = m.a0 * s;
+  m.a2 = m.a1 * s;
+  const double k = sp.kJ * ginv * inv;
+  const double bu = B0 * u0 + B1 * u1 + B2 * u2;
+  const double s2bu = s * s * bu;
+  m.j0 = k * fma(s2bu, B0, fma(s, u1 * B2 - u2 * B1, u0));
+  m.j1 = k * fma(s2bu, B1, fma(s, u2 * B0 - u0 * B2, u1));
+  m.j2 = k * fma(s2bu, B2, fma(s, u0 * B1 - u1 * B0, u2));
+  return m;
+}
+
+// Add one corner's share (weight W) of compact moments to the 13 LDS moment planes at node o,
+// expanding S-hat with the cell's B.
+__device__ __forceinline__ void expand_add(double *acc, int plane, int o, double A0, double A1,
+                                           double A2, double J0, double J1, double J2, double D,
+                                           int dens_plane, double B0, double B1, double B2) {
+  atomicAdd(&acc[0 * plane + o], fma(A2, B0 * B0, A0));
+  atomicAdd(&acc[1 * plane + o], fma(A2, B0 * B1, A1 * B2));
+  atomicAdd(&acc[2 * plane + o], fma(A2, B0 * B2, -A1 * B1));
+  atomicAdd(&acc[3 * plane + o], fma(A2, B1 * B0, -A1 * B2));
+  atomicAdd(&acc[4 * plane + o], fma(A2, B1 * B1, A0));
+  atomicAdd(&acc[5 * plane + o], fma(A2, B1 * B2, A1 * B0));
+  atomicAdd(&acc[6 * plane + o], fma(A2, B2 * B0, A1 * B1));
+  atomicAdd(&acc[7 * plane + o], fma(A2, B2 * B1, -A1 * B0));
+  atomicAdd(&acc[8 * plane + o], fma(A2, B2 * B2, A0));
+  atomicAdd(&acc[9 * plane + o], J0);
+  atomicAdd(&acc[10 * plane + o], J1);
+  atomicAdd(&acc[11 * plane + o], J2);
+  atomicAdd(&acc[dens_plane * plane + o], D);
+}
+
+// Per-lane running sum of the compact moments of consecutive particles that stay in one
+// cell, per corner (order (i,k), (i+1,k), (i,k+1), (i+1,k+1)).
+struct CellAcc {
+  double A0[4], A1[4], A2[4], J0[4], J1[4], J2[4], D[4];
+  int cell;  // tile-local column of the cell being accumulated, -1 when empty
+
+  __device__ __forceinline__ void clear() {
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < 4; ++c) A0[c] = A1[c] = A2[c] = J0[c] = J1[c] = J2[c] = D[c] = 0.0;
+  }
+  __device__ __forceinline__ void add(double fx, double fz, const Compact &m, double w) {
+    const double W[4] = {(1.0 - fx) * (1.0 - fz), fx * (1.0 - fz), (1.0 - fx) * fz, fx * fz};
 #pragma unroll
-    for (int p = 0; p < 12; ++p) atomicAdd(&acc[p * plane + o[c]], W[c] * val[p]);
-    atomicAdd(&acc[dens_plane * plane + o[c]], W[c] * w);
+    for (int c = 0; c < 4; ++c) {
+      A0[c] = fma(W[c], m.a0, A0[c]);
+      A1[c] = fma(W[c], m.a1, A1[c]);
+      A2[c] = fma(W[c], m.a2, A2[c]);
+      J0[c] = fma(W[c], m.j0, J0[c]);
+      J1[c] = fma(W[c], m.j1, J1[c]);
+      J2[c] = fma(W[c], m.j2, J2[c]);
+      D[c] = fma(W[c], w, D[c]);
+    }
+  }
+  // B is the field of the accumulated cell, whose lower-left node is (cell + 1, lz) locally.
+  __device__ __forceinline__ void flush(double *acc, int plane, int LW, int lz, int dens_plane,
+                                        double B0, double B1, double B2) {
+    const int b = lz * LW + cell + 1;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      expand_add(acc, plane, b + (c & 1) + (c >> 1) * LW, A0[c], A1[c], A2[c], J0[c], J1[c],
+                 J2[c], D[c], dens_plane, B0, B1, B2);
+  }
+};
+
+// Particles that change cell deposit into a different cell (and field) from the lane's run,
+// so they are queued per wavefront in LDS and deposited 64 at a time, one per lane.
+struct MoverQ {
+  static constexpr int kCap = 64;
+  static constexpr int kWords = 8;  // fx fz a0 a1 a2 j0 j1 j2
+  double *v;                        // [kWords][kCap]
+  int *idx;                         // [2][kCap]: accumulator node index, H^{n+3/2} index
+};
+
+__device__ __forceinline__ void drain_movers(const MoverQ &q, int count, int lane, double *acc,
+                                             int plane, int LW, int dens_plane, double w,
+                                             const double *Hn, int NPL) {
+  if (lane < count) {
+    const double fx = q.v[0 * MoverQ::kCap + lane], fz = q.v[1 * MoverQ::kCap + lane];
+    const double a0 = q.v[2 * MoverQ::kCap + lane], a1 = q.v[3 * MoverQ::kCap + lane];
+    const double a2 = q.v[4 * MoverQ::kCap + lane], j0 = q.v[5 * MoverQ::kCap + lane];
+    const double j1 = q.v[6 * MoverQ::kCap + lane], j2 = q.v[7 * MoverQ::kCap + lane];
+    const int o = q.idx[lane], hn = q.idx[MoverQ::kCap + lane];
+    const double B0 = Hn[hn], B1 = Hn[NPL + hn], B2 = Hn[2 * NPL + hn];
+#pragma unroll 1
+    for (int c = 0; c < 4; ++c) {
+      const int cx = c & 1, cz = c >> 1;
+      const double W = (cx ? fx : 1.0 - fx) * (cz ? fz : 1.0 - fz);
+      expand_add(acc, plane, o + cx + cz * LW, W * a0, W * a1, W * a2, W * j0, W * j1, W * j2,
+                 W * w, dens_plane, B0, B1, B2);
+    }
   }
 }
 
-// The 12 moment values of one particle with momentum u, Lorentz factor g and field B:
-// S-hat = w q^2 dt^2 R / (4 m g), delta-j = (w q / g) R u (the split of Eq. (3)).
-__device__ __forceinline__ void moment_values(const SpeciesArgs &sp, double g, double u0,
-                                              double u1, double u2, double B0, double B1,
-                                              double B2, double val[12]) {
-  double R[9];
-  response(sp.beta, g, B0, B1, B2, R);
-  double kS = sp.cS / g, kJ = sp.kJ / g;
-#pragma unroll
-  for (int r = 0; r < 9; ++r) val[r] = kS * R[r];
-#pragma unroll
-  for (int r = 0; r < 3; ++r) val[9 + r] = kJ * (R[3 * r] * u0 + R[3 * r + 1] * u1 + R[3 * r + 2] * u2);
-}
+// LDS layout of the particle kernel, in doubles: the moment accumulators of the tile and its
+// halo, then the fields the tile's particles read (E-bar on the tile's nodes, H^{n+1/2} on
+// its cells, H^{n+3/2} on its cells plus a one-cell ring), then the int move counters.
+struct TileLds {
+  int LW, LH, plane;          // accumulator node grid (tx + 3) x (tz + 3)
+  int EW, EPL;                // E-bar node grid (tx + 1) x (tz + 1)
+  int HPL;                    // H^{n+1/2} cells tx x tz
+  int NW, NPL;                // H^{n+3/2} cells (tx + 2) x (tz + 2)
+  size_t acc, eb, ho, hn, mq, cnt;  // offsets in doubles
+  size_t bytes;
+  __host__ __device__ TileLds(int n_planes, int tx, int tz) {
+    LW = tx + 3;
+    LH = tz + 3;
+    plane = LW * LH;
+    EW = tx + 1;
+    EPL = EW * (tz + 1);
+    HPL = tx * tz;
+    NW = tx + 2;
+    NPL = NW * (tz + 2);
+    acc = 0;
+    eb = acc + (size_t)n_planes * plane;
+    ho = eb + 3 * (size_t)EPL;
+    hn = ho + 3 * (size_t)HPL;
+    mq = hn + 3 * (size_t)NPL;
+    cnt = mq + (size_t)(kBlock / 64) * MoverQ::kCap * (MoverQ::kWords + 1);
+    bytes = cnt * sizeof(double) + (size_t)tx * tz * 10 * sizeof(int);
+  }
+};
 
+// One block per tile of cells (tile rows are cell rows), one wavefront per tile row.  The
+// row's particles (a contiguous range of the cell-sorted order) are split into 64 contiguous
+// runs, one per lane; run lengths differ by at most one.  A lane accumulates the deposits of
+// particles that stay in their cell in registers and adds them to the LDS tile when its run
+// enters the next cell, so LDS atomics are issued once per (lane, cell) instead of once per
+// particle; particles changing cell deposit directly.  The pushed state of the particle at
+// iteration `it` of lane `l` is written to location row_start + 64 it + l, which makes the
+// stores (and next cycle's loads through the permutation) coalesced.  Each lane loads the
+// state of its next particle (and the permutation entry of the one after) before pushing the
+// current one.
 template <bool PUSH>
-__global__ __launch_bounds__(kBlock) void k_particles(const StepArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_particles(const StepArgs a) {
   const GridArgs &g = a.g;
   const TileArgs &t = a.t;
-  const int tile = block_tile(t);
-  if (tile >= t.ntiles) return;
+  const int tile = block_tile(t, a.tile_list);
+  if (tile < 0) return;
   const int tzi = tile / t.ntx, txi = tile - tzi * t.ntx;
   const int i0 = txi * t.tx, k0 = tzi * t.tz;
   const int i1 = min(i0 + t.tx, g.nx), k1 = min(k0 + t.tz, g.nz);
-  const int LW = t.tx + 3, LH = t.tz + 3, plane = LW * LH;
   const int ntc = t.tx * t.tz;
+  const int64_t nn = g.nnodes, nc = g.ncells;
 
   extern __shared__ double lds[];
-  double *acc = lds;
-  int *cntL = reinterpret_cast<int *>(lds + (size_t)g.n_planes * plane);
+  const TileLds Lo(g.n_planes, t.tx, t.tz);
+  double *acc = lds + Lo.acc;
+  double *Eb = lds + Lo.eb, *Ho = lds + Lo.ho, *Hn = lds + Lo.hn;
+  int *cntL = reinterpret_cast<int *>(lds + Lo.cnt);
+  const int LW = Lo.LW, plane = Lo.plane;
 
   for (int e = threadIdx.x; e < g.n_planes * plane; e += blockDim.x) acc[e] = 0.0;
+  // stage the fields of the tile
+  for (int e = threadIdx.x; e < Lo.HPL; e += blockDim.x) {
+    const int lk = e / t.tx, li = e - lk * t.tx;
+    const int gi = i0 + li, gk = k0 + lk;
+    const bool in = gi < g.nx && gk < g.nz;
+    const int64_t c = (int64_t)gk * g.nx + gi;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) Ho[q * Lo.HPL + e] = in ? a.Hold[q * nc + c] : 0.0;
+  }
+  if (PUSH) {
+    for (int e = threadIdx.x; e < Lo.EPL; e += blockDim.x) {
+      const int lk = e / Lo.EW, li = e - lk * Lo.EW;
+      int gi = i0 + li;
+      const int gk = wrap_any(k0 + lk, g.nz);
+      bool in = true;
+      if (g.bc_x == PIC_BC_PERIODIC) gi = wrap_any(gi, g.nx); else in = gi <= g.nx;
+      const int64_t n = (int64_t)gk * g.nxn + gi;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) Eb[q * Lo.EPL + e] = in ? a.Ebar[q * nn + n] : 0.0;
+    }
+    for (int e = threadIdx.x; e < Lo.NPL; e += blockDim.x) {
+      const int lk = e / Lo.NW, li = e - lk * Lo.NW;
+      int gi = i0 - 1 + li;
+      const int gk = wrap_any(k0 - 1 + lk, g.nz);
+      bool in = true;
+      if (g.bc_x == PIC_BC_PERIODIC) gi = wrap_any(gi, g.nx); else in = gi >= 0 && gi < g.nx;
+      const int64_t c = (int64_t)gk * g.nx + gi;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) Hn[q * Lo.NPL + e] = in ? a.Hnew[q * nc + c] : 0.0;
+    }
+  }
   __syncthreads();
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nwaves = blockDim.x >> 6;
-  const int64_t nn = g.nnodes, nc = g.ncells;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  MoverQ mq;
+  mq.v = lds + Lo.mq + (size_t)wave * MoverQ::kCap * (MoverQ::kWords + 1);
+  mq.idx = reinterpret_cast<int *>(mq.v + MoverQ::kCap * MoverQ::kWords);
 
   for (int s = 0; s < a.nsp; ++s) {
     const SpeciesArgs &sp = a.sp[s];
@@ -266,100 +435,226 @@ __global__ __launch_bounds__(kBlock) void k_particles(const StepArgs a) {
       for (int e = threadIdx.x; e < ntc * 10; e += blockDim.x) cntL[e] = 0;
       __syncthreads();
     }
+    const double *sx = sp.src[0], *sz = sp.src[1], *su0 = sp.src[2], *su1 = sp.src[3], *su2 = sp.src[4];
+    const int dens = 12 + s;
     for (int r = k0 + wave; r < k1; r += nwaves) {
       const int64_t rowc = (int64_t)r * g.nx;
       const int jb = sp.cs[rowc + i0], je = sp.cs[rowc + i1];
-      for (int j = jb + lane; j < je; j += 64) {
-        const int p = sp.perm[j];
-        const double x = sp.src[0][p], z = sp.src[1][p];
-        const double u0 = sp.src[2][p], u1 = sp.src[3][p], u2 = sp.src[4][p];
-        const int i = (int)floor(x), k = (int)floor(z);
-        if (k != r || i < i0 || i >= i1) {
-          atomicOr(a.flags, kFlagOrder);
-          if (PUSH) sp.code[j] = kAbsorbed;
-          continue;
-        }
-        const double fx = x - (double)i, fz = z - (double)k;
-        const int64_t c = (int64_t)k * g.nx + i;
-        const double B0 = a.Hold[c], B1 = a.Hold[nc + c], B2 = a.Hold[2 * nc + c];
-        const double gam = sqrt(1.0 + u0 * u0 + u1 * u1 + u2 * u2);
-        const int lx = i - i0 + 1, lz = k - k0 + 1;
-        if (!PUSH) {
-          double val[12];
-          moment_values(sp, gam, u0, u1, u2, B0, B1, B2, val);
-          deposit_lds(acc, plane, LW, lx, lz, fx, fz, val, 12 + s, sp.w);
-          continue;
-        }
-        // gather E-bar at x^{n+1/2} from the 4 corner nodes (linear weights)
-        const int in1 = (g.bc_x == PIC_BC_PERIODIC) ? wrap1(i + 1, g.nx) : i + 1;
-        const int kn1 = wrap1(k + 1, g.nz);
-        const int64_t n00 = (int64_t)k * g.nxn + i, n10 = (int64_t)k * g.nxn + in1;
-        const int64_t n01 = (int64_t)kn1 * g.nxn + i, n11 = (int64_t)kn1 * g.nxn + in1;
-        const double W0 = (1.0 - fx) * (1.0 - fz), W1 = fx * (1.0 - fz);
-        const double W2 = (1.0 - fx) * fz, W3 = fx * fz;
-        double Ep[3];
+      const int L = je - jb;
+      if (L == 0) continue;
+      const int q = L >> 6, rr = L & 63;
+      const int my_n = q + (lane < rr ? 1 : 0);
+      const int start = jb + lane * q + min(lane, rr);
+      const int iters = q + (rr > 0 ? 1 : 0);
+      const int lz = r - k0 + 1;
+      const int lk = r - k0;
+      CellAcc ca;
+      ca.clear();
+      ca.cell = -1;
+      int nq = 0;  // movers queued by this wavefront (uniform)
+      int fcell = -1;
+      double fB0 = 0.0, fB1 = 0.0, fB2 = 0.0, fE[12];
+      // The run is processed in chunks of kChunk particles: the chunk's state loads are issued
+      // together (and the next chunk's permutation entries), then the chunk is pushed from
+      // registers.  Global stores share the vector-memory counter with loads, so waiting for a
+      // load also waits for earlier stores; chunking pays that wait once per chunk.
+      constexpr int kChunk = 4;
+      double cx_[kChunk], cz_[kChunk], c0_[kChunk], c1_[kChunk], c2_[kChunk];
+      int cp_[kChunk], np_[kChunk];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          const double *f = a.Ebar + q * nn;
-          Ep[q] = W0 * f[n00] + W1 * f[n10] + W2 * f[n01] + W3 * f[n11];
+      for (int k = 0; k < kChunk; ++k) np_[k] = (k < my_n) ? sp.perm[start + k] : 0;
+      // all lanes run the same number of iterations so the mover queue stays wave-uniform
+      for (int it = 0; it < iters; ++it) {
+        if (it % kChunk == 0) {
+#pragma unroll
+          for (int k = 0; k < kChunk; ++k) {
+            cp_[k] = np_[k];
+            const bool v = it + k < my_n;
+            cx_[k] = v ? sx[cp_[k]] : 0.0;
+            cz_[k] = v ? sz[cp_[k]] : 0.0;
+            c0_[k] = v ? su0[cp_[k]] : 0.0;
+            c1_[k] = v ? su1[cp_[k]] : 0.0;
+            c2_[k] = v ? su2[cp_[k]] : 0.0;
+          }
+#pragma unroll
+          for (int k = 0; k < kChunk; ++k)
+            np_[k] = (it + kChunk + k < my_n) ? sp.perm[start + it + kChunk + k] : 0;
         }
-        // implicit push: u-bar = R (u + beta E), u' = 2 u-bar - u
-        double R[9];
-        response(sp.beta, gam, B0, B1, B2, R);
-        const double av0 = u0 + sp.beta * Ep[0], av1 = u1 + sp.beta * Ep[1], av2 = u2 + sp.beta * Ep[2];
-        const double n0 = 2.0 * (R[0] * av0 + R[1] * av1 + R[2] * av2) - u0;
-        const double n1 = 2.0 * (R[3] * av0 + R[4] * av1 + R[5] * av2) - u1;
-        const double n2 = 2.0 * (R[6] * av0 + R[7] * av1 + R[8] * av2) - u2;
-        const double g1 = sqrt(1.0 + n0 * n0 + n1 * n1 + n2 * n2);
-        double xn = x + g.cx * (n0 / g1);
-        double zn = z + g.cz * (n2 / g1);
-        bool alive = true;
-        if (g.bc_x == PIC_BC_PERIODIC) {
-          if (xn < 0.0) xn += (double)g.nx;
-          if (xn >= (double)g.nx) xn -= (double)g.nx;
-        } else if (xn < 0.0 || xn >= (double)g.nx) {
-          alive = false;
+        const bool act = it < my_n;
+        const int j = start + it;
+        const int p = cp_[0];
+        const double x = cx_[0], z = cz_[0], u0 = c0_[0], u1 = c1_[0], u2 = c2_[0];
+#pragma unroll
+        for (int k = 0; k + 1 < kChunk; ++k) {
+          cp_[k] = cp_[k + 1];
+          cx_[k] = cx_[k + 1];
+          cz_[k] = cz_[k + 1];
+          c0_[k] = c0_[k + 1];
+          c1_[k] = c1_[k + 1];
+          c2_[k] = c2_[k + 1];
         }
-        if (zn < 0.0) zn += (double)g.nz;
-        if (zn >= (double)g.nz) zn -= (double)g.nz;
-        if (!(isfinite(g1) && isfinite(xn) && isfinite(zn))) {
-          atomicOr(a.flags, kFlagNonFinite);
-          alive = false;
-        }
-        uint8_t code = kAbsorbed;
-        int i2 = 0, k2 = 0, di = 0, dk = 0;
-        if (alive) {
-          i2 = (int)floor(xn);
-          k2 = (int)floor(zn);
-          di = i2 - i;
-          dk = k2 - k;
-          if (di > 1) di -= g.nx;
-          if (di < -1) di += g.nx;
-          if (dk > 1) dk -= g.nz;
-          if (dk < -1) dk += g.nz;
-          if (di < -1 || di > 1 || dk < -1 || dk > 1) {
-            atomicOr(a.flags, kFlagJump);
-            alive = false;
+        bool mover = false;
+        int mo = 0, mh = 0;
+        double mfx = 0, mfz = 0;
+        Compact mm = {0, 0, 0, 0, 0, 0};
+        const int i = (int)floor(x), k = (int)floor(z);
+        if (act && (k != r || i < i0 || i >= i1)) {
+          atomicOr(a.flags, kFlagOrder);
+          if (PUSH) sp.locode[j] = ((uint32_t)(jb + it * 64 + lane) << 4) | kAbsorbed;
+        } else if (act) {
+          const int li = i - i0;
+          const double fx = x - (double)i, fz = z - (double)k;
+          const int hc = lk * t.tx + li;
+          const double gam = sqrt(1.0 + u0 * u0 + u1 * u1 + u2 * u2);
+          if (li != ca.cell) {
+            if (ca.cell >= 0) {
+              if (PUSH) {
+                const int hn = (lk + 1) * Lo.NW + ca.cell + 1;
+                ca.flush(acc, plane, LW, lz, dens, Hn[hn], Hn[Lo.NPL + hn], Hn[2 * Lo.NPL + hn]);
+              } else {
+                const int ho = lk * t.tx + ca.cell;
+                ca.flush(acc, plane, LW, lz, dens, Ho[ho], Ho[Lo.HPL + ho], Ho[2 * Lo.HPL + ho]);
+              }
+              ca.clear();
+            }
+            ca.cell = li;
+          }
+          if (li != fcell) {
+            // fields of the run's cell, kept in registers while the run stays in it
+            fcell = li;
+            fB0 = Ho[hc];
+            fB1 = Ho[Lo.HPL + hc];
+            fB2 = Ho[2 * Lo.HPL + hc];
+            if (PUSH) {
+              const int e00 = lk * Lo.EW + li;
+#pragma unroll
+              for (int qq = 0; qq < 3; ++qq) {
+                const double *f = Eb + qq * Lo.EPL + e00;
+                fE[4 * qq] = f[0];
+                fE[4 * qq + 1] = f[1];
+                fE[4 * qq + 2] = f[Lo.EW];
+                fE[4 * qq + 3] = f[Lo.EW + 1];
+              }
+            }
+          }
+          const double B0 = fB0, B1 = fB1, B2 = fB2;
+          if (!PUSH) {
+            ca.add(fx, fz, compact_moments(sp, gam, u0, u1, u2, B0, B1, B2), sp.w);
           } else {
-            code = (uint8_t)((dk + 1) * 3 + (di + 1));
+            // gather E-bar at x^{n+1/2} from the 4 corner nodes (linear weights)
+            const double W0 = (1.0 - fx) * (1.0 - fz), W1 = fx * (1.0 - fz);
+            const double W2 = (1.0 - fx) * fz, W3 = fx * fz;
+            double Ep[3];
+#pragma unroll
+            for (int qq = 0; qq < 3; ++qq)
+              Ep[qq] = W0 * fE[4 * qq] + W1 * fE[4 * qq + 1] + W2 * fE[4 * qq + 2] + W3 * fE[4 * qq + 3];
+            // implicit push: u-bar = R (u + beta E), u' = 2 u-bar - u
+            double R[9];
+            response(sp.beta, gam, B0, B1, B2, R);
+            const double av0 = u0 + sp.beta * Ep[0], av1 = u1 + sp.beta * Ep[1], av2 = u2 + sp.beta * Ep[2];
+            const double n0 = 2.0 * (R[0] * av0 + R[1] * av1 + R[2] * av2) - u0;
+            const double n1 = 2.0 * (R[3] * av0 + R[4] * av1 + R[5] * av2) - u1;
+            const double n2 = 2.0 * (R[6] * av0 + R[7] * av1 + R[8] * av2) - u2;
+            const double g1 = sqrt(1.0 + n0 * n0 + n1 * n1 + n2 * n2);
+            double xn = x + g.cx * (n0 / g1);
+            double zn = z + g.cz * (n2 / g1);
+            bool alive = true;
+            if (g.bc_x == PIC_BC_PERIODIC) {
+              if (xn < 0.0) xn += (double)g.nx;
+              if (xn >= (double)g.nx) xn -= (double)g.nx;
+            } else if (xn < 0.0 || xn >= (double)g.nx) {
+              alive = false;
+            }
+            if (zn < 0.0) zn += (double)g.nz;
+            if (zn >= (double)g.nz) zn -= (double)g.nz;
+            if (!(isfinite(g1) && isfinite(xn) && isfinite(zn))) {
+              atomicOr(a.flags, kFlagNonFinite);
+              alive = false;
+            }
+            uint32_t code = kAbsorbed;
+            int i2 = 0, k2 = 0, di = 0, dk = 0;
+            if (alive) {
+              i2 = (int)floor(xn);
+              k2 = (int)floor(zn);
+              di = i2 - i;
+              dk = k2 - k;
+              if (di > 1) di -= g.nx;
+              if (di < -1) di += g.nx;
+              if (dk > 1) dk -= g.nz;
+              if (dk < -1) dk += g.nz;
+              if (di < -1 || di > 1 || dk < -1 || dk > 1) {
+                atomicOr(a.flags, kFlagJump);
+                alive = false;
+              } else {
+                code = (uint32_t)((dk + 1) * 3 + (di + 1));
+              }
+            }
+            const int loc = jb + it * 64 + lane;
+            sp.dst[0][loc] = xn;
+            sp.dst[1][loc] = zn;
+            sp.dst[2][loc] = n0;
+            sp.dst[3][loc] = n1;
+            sp.dst[4][loc] = n2;
+            if (sp.dst_id) sp.dst_id[loc] = sp.src_id[p];
+            sp.locode[j] = ((uint32_t)loc << 4) | code;
+            atomicAdd(&cntL[hc * 10 + code], 1);
+            if (alive) {
+              // deposit M^{n+3/2} at x^{n+3/2} with u^{n+1}, gamma(u^{n+1}) and H^{n+3/2} there
+              const int hn = (lk + dk + 1) * Lo.NW + (li + di + 1);
+              const Compact m = compact_moments(sp, g1, n0, n1, n2, Hn[hn], Hn[Lo.NPL + hn], Hn[2 * Lo.NPL + hn]);
+              const double fx2 = xn - (double)i2, fz2 = zn - (double)k2;
+              if (code == 4u) {
+                ca.add(fx2, fz2, m, sp.w);
+              } else {
+                mover = true;
+                mo = (lz + dk) * LW + (li + 1 + di);
+                mh = hn;
+                mfx = fx2;
+                mfz = fz2;
+                mm = m;
+              }
+            }
           }
         }
-        sp.dst[0][j] = xn;
-        sp.dst[1][j] = zn;
-        sp.dst[2][j] = n0;
-        sp.dst[3][j] = n1;
-        sp.dst[4][j] = n2;
-        if (sp.dst_id) sp.dst_id[j] = sp.src_id[p];
-        sp.code[j] = code;
-        atomicAdd(&cntL[((k - k0) * t.tx + (i - i0)) * 10 + code], 1);
-        if (alive) {
-          // deposit M^{n+3/2} at x^{n+3/2} with u^{n+1}, gamma(u^{n+1}) and H^{n+3/2} there
-          const int64_t c2 = (int64_t)k2 * g.nx + i2;
-          double val[12];
-          moment_values(sp, g1, n0, n1, n2, a.Hnew[c2], a.Hnew[nc + c2], a.Hnew[2 * nc + c2], val);
-          deposit_lds(acc, plane, LW, lx + di, lz + dk, xn - (double)i2, zn - (double)k2, val,
-                      12 + s, sp.w);
+        if (PUSH) {
+          // queue this iteration's movers; drain first if they would not fit
+          const uint64_t mmask = __ballot(mover);
+          const int nm = __popcll(mmask);
+          if (nq + nm > MoverQ::kCap) {
+            wave_sync();
+            drain_movers(mq, nq, lane, acc, plane, LW, dens, sp.w, Hn, Lo.NPL);
+            wave_sync();
+            nq = 0;
+          }
+          if (mover) {
+            const int e = nq + __popcll(mmask & lt_mask);
+            mq.v[0 * MoverQ::kCap + e] = mfx;
+            mq.v[1 * MoverQ::kCap + e] = mfz;
+            mq.v[2 * MoverQ::kCap + e] = mm.a0;
+            mq.v[3 * MoverQ::kCap + e] = mm.a1;
+            mq.v[4 * MoverQ::kCap + e] = mm.a2;
+            mq.v[5 * MoverQ::kCap + e] = mm.j0;
+            mq.v[6 * MoverQ::kCap + e] = mm.j1;
+            mq.v[7 * MoverQ::kCap + e] = mm.j2;
+            mq.idx[e] = mo;
+            mq.idx[MoverQ::kCap + e] = mh;
+          }
+          nq += nm;
         }
+      }
+      if (ca.cell >= 0) {
+        if (PUSH) {
+          const int hn = (lk + 1) * Lo.NW + ca.cell + 1;
+          ca.flush(acc, plane, LW, lz, dens, Hn[hn], Hn[Lo.NPL + hn], Hn[2 * Lo.NPL + hn]);
+        } else {
+          const int ho = lk * t.tx + ca.cell;
+          ca.flush(acc, plane, LW, lz, dens, Ho[ho], Ho[Lo.HPL + ho], Ho[2 * Lo.HPL + ho]);
+        }
+      }
+      if (PUSH && nq > 0) {
+        wave_sync();
+        drain_movers(mq, nq, lane, acc, plane, LW, dens, sp.w, Hn, Lo.NPL);
+        wave_sync();
       }
     }
     if (PUSH) {
@@ -368,8 +663,8 @@ __global__ __launch_bounds__(kBlock) void k_particles(const StepArgs a) {
       for (int e = threadIdx.x; e < (k1 - k0) * cw * kMoveCodes; e += blockDim.x) {
         const int d = e / ((k1 - k0) * cw);
         const int rem = e - d * ((k1 - k0) * cw);
-        const int lk = rem / cw, li = rem - lk * cw;
-        sp.cnt[(int64_t)d * nc + (int64_t)(k0 + lk) * g.nx + (i0 + li)] = cntL[(lk * t.tx + li) * 10 + d];
+        const int lkk = rem / cw, li = rem - lkk * cw;
+        sp.cnt[(int64_t)d * nc + (int64_t)(k0 + lkk) * g.nx + (i0 + li)] = cntL[(lkk * t.tx + li) * 10 + d];
       }
       __syncthreads();
     }
@@ -380,8 +675,8 @@ __global__ __launch_bounds__(kBlock) void k_particles(const StepArgs a) {
     const double v = acc[e];
     if (v == 0.0) continue;
     const int p = e / plane, idx = e - p * plane;
-    const int lz = idx / LW, lx = idx - lz * LW;
-    int gx = i0 - 1 + lx, gz = k0 - 1 + lz;
+    const int lzz = idx / LW, lx = idx - lzz * LW;
+    int gx = i0 - 1 + lx, gz = k0 - 1 + lzz;
     if (g.bc_x == PIC_BC_PERIODIC) {
       gx = wrap_any(gx, g.nx);
     } else if (gx < 0 || gx > g.nx) {
@@ -396,17 +691,24 @@ __global__ __launch_bounds__(kBlock) void k_particles(const StepArgs a) {
 // Sort
 // ------------------------------------------------------------------------------------------
 
-// Source cell of destination cell (iK, kK) for move code d, or -1 if it does not exist.
-__device__ __forceinline__ int64_t source_cell(const GridArgs &g, int iK, int kK, int d) {
+// Source cell of destination cell (iK, kK) for move code d, or -1 if it does not exist; its
+// column and row are returned in is, ks.
+__device__ __forceinline__ int64_t source_cell(const GridArgs &g, int iK, int kK, int d, int &is,
+                                               int &ks) {
   const int di = d % 3 - 1, dk = d / 3 - 1;
-  int is = iK - di, ks = kK - dk;
+  is = iK - di;
+  ks = wrap1(kK - dk, g.nz);
   if (g.bc_x == PIC_BC_PERIODIC) {
-    is = wrap_any(is, g.nx);
+    is = wrap1(is, g.nx);
   } else if (is < 0 || is >= g.nx) {
     return -1;
   }
-  ks = wrap_any(ks, g.nz);
   return (int64_t)ks * g.nx + is;
+}
+
+// Whether the cell (is, ks) lies in a tile that held particles (its counts are valid).
+__device__ __forceinline__ bool cell_tile_active(const StepArgs &a, int is, int ks) {
+  return a.tile_active[a.row_tile[ks] * a.t.ntx + a.col_tile[is]] != 0;
 }
 
 __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
@@ -449,8 +751,9 @@ __global__ __launch_bounds__(kBlock) void k_scan_counts(const StepArgs a) {
     if (c < g.ncells) {
       const int kK = (int)(c / g.nx), iK = (int)(c - (int64_t)kK * g.nx);
       for (int d = 0; d < kMoveCodes; ++d) {
-        const int64_t src = source_cell(g, iK, kK, d);
-        if (src >= 0) v += sp.cnt[(int64_t)d * g.ncells + src];
+        int is, ks;
+        const int64_t src = source_cell(g, iK, kK, d, is, ks);
+        if (src >= 0 && cell_tile_active(a, is, ks)) v += sp.cnt[(int64_t)d * g.ncells + src];
       }
     }
     in[q] = v;
@@ -494,49 +797,99 @@ __global__ __launch_bounds__(kBlock) void k_scan_finish(const StepArgs a) {
   }
 }
 
-// First slot, in the next order, of the particles moving from cell c with move code d:
-// start of the destination cell plus everything arriving there from source cells that come
-// earlier in the current (cell-sorted) order.
-__device__ int64_t dest_base(const GridArgs &g, const SpeciesArgs &sp, int ic, int kc, int d) {
+// First slot, in the next order, of the particles moving from cell (ic, kc) with move code
+// d: start of the destination cell plus everything arriving there from source cells that
+// come earlier in the current (cell-sorted) order.  cntv(is, ks, d) gives the counts,
+// csn(iK, kK) the next order's cell starts.  Returns 0 for a destination outside an
+// absorbing x axis (no particle carries such a code).
+template <typename Cnt, typename Csn>
+__device__ int dest_base(const GridArgs &g, int ic, int kc, int d, Cnt cntv, Csn csn) {
   const int di = d % 3 - 1, dk = d / 3 - 1;
-  int iK = ic + di, kK = wrap_any(kc + dk, g.nz);
-  if (g.bc_x == PIC_BC_PERIODIC) iK = wrap_any(iK, g.nx);
-  const int64_t K = (int64_t)kK * g.nx + iK;
+  int iK = ic + di;
+  const int kK = wrap1(kc + dk, g.nz);
+  if (g.bc_x == PIC_BC_PERIODIC) {
+    iK = wrap1(iK, g.nx);
+  } else if (iK < 0 || iK >= g.nx) {
+    return 0;
+  }
   const int64_t key_c = (int64_t)kc * g.nx + ic;
-  int64_t base = sp.cs_new[K];
+  int base = csn(iK, kK);
   for (int d2 = 0; d2 < kMoveCodes; ++d2) {
-    const int64_t src = source_cell(g, iK, kK, d2);
-    if (src >= 0 && src < key_c) base += sp.cnt[(int64_t)d2 * g.ncells + src];
+    int is, ks;
+    const int64_t src = source_cell(g, iK, kK, d2, is, ks);
+    if (src >= 0 && src < key_c) base += cntv(is, ks, d2);
   }
   return base;
 }
 
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-
+// Stable destinations of one tile's particles.  The destination base of every (cell, move
+// code) of the tile is computed once into LDS; then one wavefront per tile row walks the row's
+// slots in order, 64 at a time: particles with the same (cell, code) in a group of 64 get
+// consecutive ranks by ballot, and a per-wave LDS counter carries the rank across groups.
 __global__ __launch_bounds__(kBlock) void k_rank(const StepArgs a) {
   const GridArgs &g = a.g;
   const TileArgs &t = a.t;
-  const int tile = block_tile(t);
-  if (tile >= t.ntiles) return;
+  const int tile = block_tile(t, a.tile_list);
+  if (tile < 0) return;
   const int tzi = tile / t.ntx, txi = tile - tzi * t.ntx;
   const int i0 = txi * t.tx, k0 = tzi * t.tz;
   const int i1 = min(i0 + t.tx, g.nx), k1 = min(k0 + t.tz, g.nz);
-  const int cw = i1 - i0;
+  const int cw = i1 - i0, ch = k1 - k0;
+  const int ntc = t.tx * t.tz;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nwaves = blockDim.x >> 6;
   extern __shared__ int ldsi[];
-  int *rowcs = ldsi + wave * (t.tx + 1);                           // [tx + 1] per wave
-  int *ctr = ldsi + nwaves * (t.tx + 1) + wave * (t.tx * 10);      // [tx][10] per wave
+  const int ring_cells = (t.tx + 4) * (t.tz + 4);
+  int *btab = ldsi;                                                   // [ntc][9]
+  int *rowcs = ldsi + ntc * 9 + wave * (t.tx + 1);                    // [tx + 1] per wave
+  int *ctr = ldsi + ntc * 9 + nwaves * (t.tx + 1) + wave * (t.tx * 10);  // [tx][10] per wave
+  int *rcnt = ldsi + ntc * 9 + nwaves * (t.tx + 1 + t.tx * 10);       // [9][ring_cells]
+  int *rcsn = rcnt + kMoveCodes * ring_cells;                         // [ring_cells]
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
   for (int s = 0; s < a.nsp; ++s) {
     const SpeciesArgs &sp = a.sp[s];
     if (!sp.active) continue;
+    bool mine = false;
+    for (int r = k0 + threadIdx.x; r < k1; r += blockDim.x)
+      mine = mine || sp.cs[(int64_t)r * g.nx + i1] > sp.cs[(int64_t)r * g.nx + i0];
+    if (!__syncthreads_or(mine)) continue;
+    // counts of the tile and a one-cell ring (sources of the destinations reached from the
+    // tile), and next-order starts of the same region, staged in LDS
+    const int RW = t.tx + 4, RH = t.tz + 4;  // ring of two cells: destinations +-1, their sources +-1
+    for (int e = threadIdx.x; e < RW * RH; e += blockDim.x) {
+      const int rz = e / RW, rx = e - rz * RW;
+      int gi = i0 - 2 + rx;
+      const int gk = wrap_any(k0 - 2 + rz, g.nz);
+      bool in = true;
+      if (g.bc_x == PIC_BC_PERIODIC) gi = wrap_any(gi, g.nx); else in = gi >= 0 && gi < g.nx;
+      const int64_t c = (int64_t)gk * g.nx + gi;
+      const bool act = in && cell_tile_active(a, gi, gk);
+#pragma unroll
+      for (int d = 0; d < kMoveCodes; ++d) rcnt[d * RW * RH + e] = act ? sp.cnt[(int64_t)d * g.ncells + c] : 0;
+      rcsn[e] = in ? sp.cs_new[c] : 0;
+    }
+    __syncthreads();
+    // local ring coordinates of a global cell near the tile (periodic wrap on both axes)
+    auto ring = [&](int gi, int gk) {
+      int rx = gi - (i0 - 2), rz = gk - (k0 - 2);
+      if (rx < 0) rx += g.nx; else if (rx >= RW) rx -= g.nx;
+      if (rz < 0) rz += g.nz; else if (rz >= RH) rz -= g.nz;
+      return rz * RW + rx;
+    };
+    auto cntv = [&](int is, int ks, int d) { return rcnt[d * RW * RH + ring(is, ks)]; };
+    auto csn = [&](int iK, int kK) { return rcsn[ring(iK, kK)]; };
+    for (int e = threadIdx.x; e < ch * cw * kMoveCodes; e += blockDim.x) {
+      const int cell = e / kMoveCodes, d = e - cell * kMoveCodes;
+      const int lk = cell / cw, li = cell - lk * cw;
+      int b = 0;
+      if (rcnt[d * RW * RH + (lk + 2) * RW + (li + 2)] > 0) b = dest_base(g, i0 + li, k0 + lk, d, cntv, csn);
+      btab[(lk * t.tx + li) * kMoveCodes + d] = b;
+    }
+    __syncthreads();
     const int total = sp.cs_new[g.ncells];
     for (int r = k0 + wave; r < k1; r += nwaves) {
       const int64_t rowc = (int64_t)r * g.nx;
+      const int lk = r - k0;
       for (int q = lane; q <= cw; q += 64) rowcs[q] = sp.cs[rowc + i0 + q];
       for (int q = lane; q < cw * 10; q += 64) ctr[q] = 0;
       wave_sync();
@@ -544,9 +897,11 @@ __global__ __launch_bounds__(kBlock) void k_rank(const StepArgs a) {
       for (int base = jb; base < je; base += 64) {
         const int j = base + lane;
         const bool act = j < je;
-        int d = kAbsorbed, cl = 0;
+        int d = kAbsorbed, cl = 0, loc = 0;
         if (act) {
-          d = sp.code[j];
+          const uint32_t lc = sp.locode[j];
+          d = (int)(lc & 15u);
+          loc = (int)(lc >> 4);
           int lo = 0, hi = cw - 1;  // largest cl with rowcs[cl] <= j
           while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -563,11 +918,11 @@ __global__ __launch_bounds__(kBlock) void k_rank(const StepArgs a) {
           const uint64_t grp = __ballot(valid && key == lkey);
           const int lcl = lkey / 10, ld = lkey - lcl * 10;
           const int before = ctr[lkey];
-          const int64_t b0 = dest_base(g, sp, i0 + lcl, r, ld) + before;
+          const int b0 = btab[(lk * t.tx + lcl) * kMoveCodes + ld] + before;
           if ((grp >> lane) & 1ull) {
-            const int64_t slot = b0 + __popcll(grp & lt_mask);
+            const int slot = b0 + __popcll(grp & lt_mask);
             if (slot >= 0 && slot < total) {
-              sp.perm_new[slot] = j;
+              sp.perm_new[slot] = loc;
             } else {
               atomicOr(a.flags, kFlagSlot);
             }
@@ -580,7 +935,44 @@ __global__ __launch_bounds__(kBlock) void k_rank(const StepArgs a) {
       }
       wave_sync();
     }
+    __syncthreads();
   }
+}
+
+// Flag per tile: does it hold particles of any species in the order given by the cell starts
+// (the current order, or the next one when from_next is set).
+__global__ __launch_bounds__(kBlock) void k_tile_flags(const StepArgs a, int from_next) {
+  const GridArgs &g = a.g;
+  const TileArgs &t = a.t;
+  const int tile = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tile >= t.ntiles) return;
+  const int tzi = tile / t.ntx, txi = tile - tzi * t.ntx;
+  const int i0 = txi * t.tx, k0 = tzi * t.tz;
+  const int i1 = min(i0 + t.tx, g.nx), k1 = min(k0 + t.tz, g.nz);
+  int act = 0;
+  for (int s = 0; s < a.nsp; ++s) {
+    const SpeciesArgs &sp = a.sp[s];
+    if (!sp.active) continue;
+    const int32_t *cs = from_next ? sp.cs_new : sp.cs;
+    for (int r = k0; r < k1; ++r) act |= cs[(int64_t)r * g.nx + i1] > cs[(int64_t)r * g.nx + i0];
+  }
+  a.tile_active_next[tile] = (uint8_t)act;
+}
+
+// Ordered list of the flagged tiles (one block, block-wide scans), count at [ntiles].
+__global__ __launch_bounds__(1024) void k_tile_compact(const StepArgs a) {
+  __shared__ int sh[1024 / 64];
+  const TileArgs &t = a.t;
+  int carry = 0;
+  for (int base = 0; base < t.ntiles; base += blockDim.x) {
+    const int tile = base + threadIdx.x;
+    const int act = (tile < t.ntiles) ? a.tile_active_next[tile] : 0;
+    int total;
+    const int off = block_excl_scan(act, sh, &total);
+    if (act) a.tile_list_next[carry + off] = tile;
+    carry += total;
+  }
+  if (threadIdx.x == 0) a.tile_list_next[t.ntiles] = carry;
 }
 
 __global__ void k_iota(int32_t *p, int64_t n) {
@@ -591,13 +983,14 @@ __global__ void k_iota(int32_t *p, int64_t n) {
 }  // namespace
 
 size_t particle_lds_bytes(const GridArgs &g, const TileArgs &t) {
-  return (size_t)g.n_planes * (t.tx + 3) * (t.tz + 3) * sizeof(double) +
-         (size_t)t.tx * t.tz * 10 * sizeof(int);
+  return TileLds(g.n_planes, t.tx, t.tz).bytes;
 }
 
 size_t rank_lds_bytes(const TileArgs &t) {
   const int nw = kBlock / 64;
-  return (size_t)nw * ((t.tx + 1) + t.tx * 10) * sizeof(int);
+  const size_t ring = (size_t)(t.tx + 4) * (t.tz + 4);
+  return ((size_t)t.tx * t.tz * kMoveCodes + (size_t)nw * ((t.tx + 1) + t.tx * 10) +
+          ring * (kMoveCodes + 1)) * sizeof(int);
 }
 
 hipError_t launch_field_solve(const FieldArgs &a, hipStream_t s) {
@@ -622,7 +1015,17 @@ hipError_t launch_sort(const StepArgs &a, int32_t n_scan_blocks, hipStream_t s) 
   hipLaunchKernelGGL(k_scan_counts, dim3((unsigned)n_scan_blocks, (unsigned)a.nsp), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)a.nsp), dim3(1024), 0, s, a, n_scan_blocks);
   hipLaunchKernelGGL(k_scan_finish, dim3((unsigned)n_scan_blocks, (unsigned)a.nsp), dim3(kBlock), 0, s, a);
+  const unsigned ntb = (unsigned)((a.t.ntiles + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_tile_flags, dim3(ntb), dim3(kBlock), 0, s, a, 1);
+  hipLaunchKernelGGL(k_tile_compact, dim3(1), dim3(1024), 0, s, a);
   hipLaunchKernelGGL(k_rank, dim3(8u * (unsigned)a.t.per_xcd), dim3(kBlock), rank_lds_bytes(a.t), s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_list(const StepArgs &a, bool from_next_order, hipStream_t s) {
+  const unsigned ntb = (unsigned)((a.t.ntiles + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_tile_flags, dim3(ntb), dim3(kBlock), 0, s, a, from_next_order ? 1 : 0);
+  hipLaunchKernelGGL(k_tile_compact, dim3(1), dim3(1024), 0, s, a);
   return hipGetLastError();
 }
 

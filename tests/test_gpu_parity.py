@@ -118,7 +118,7 @@ def small_workloads():
 SMALL = small_workloads()
 
 
-@pytest.mark.parametrize("tile", [(0, 0), (1, 1), (4, 4), (8, 2), (16, 16)])
+@pytest.mark.parametrize("tile", [(0, 0), (1, 1), (4, 4), (8, 2), (16, 8)])
 @pytest.mark.parametrize("wi", range(len(SMALL)))
 def test_load_sort_and_deposit(pic, wi, tile):
     wl = SMALL[wi]
@@ -262,6 +262,11 @@ def test_argument_errors(pic):
         ctx.load_particles(1, -1.0, 1.0, 1.0, [1.0], [0.5], [0.0], [0.0], [0.0])
     assert e.value.status == 1
     ctx.close()
+    big = pic.Context(g, tile=(64, 64))   # LDS accumulators of such a tile exceed 64 KiB
+    with pytest.raises(pic.PicError) as e:
+        big.load_particles(0, -1.0, 1.0, 1.0, [1.0], [0.5], [0.0], [0.0], [0.0])
+    assert e.value.status == 1 and "tile too large" in str(e.value)
+    big.close()
 
 
 def test_tile_size_invariance(pic):
@@ -269,7 +274,7 @@ def test_tile_size_invariance(pic):
     wl = picgen.random_small(5, nx=37, nz=29, ppc=6, bc_x=1, dx=0.5, dz=0.5, dt=0.4)
     _say("tile invariance")
     res = []
-    for tile in [(4, 4), (8, 8), (16, 16), (5, 3)]:
+    for tile in [(4, 4), (8, 8), (16, 8), (5, 3), (32, 4)]:
         ctx = pic.Context(wl.grid, track_ids=True, tile=tile)
         for s, sp in enumerate(wl.species):
             ctx.load_particles(s, sp.q, sp.m, sp.w, sp.xi_x, sp.xi_z, sp.ux, sp.uy, sp.uz)
