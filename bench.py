@@ -9,7 +9,9 @@ in host memory, loaded once, and are resident in HBM before the timed region sta
 
 Prints one JSON line with the throughput (alive particles x steps / s over whole cycles),
 the roofline position of the dominant kernel (the fused particle kernel) measured with HIP
-events on the stream the kernels run on, and the CPU oracle timed on a bounded sample.
+events on the stream the kernels run on, and the CPU oracle timed on a bounded sample.  The
+line also carries the FP64 / mixed-precision comparison: the same foil workload in both
+precisions, and the dense foil (200 n_c, 128 particles per cell and species) in both.
 """
 from __future__ import annotations
 
@@ -28,9 +30,10 @@ import picgen  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes of the fused particle kernel: each particle's state is read and written
-# once (FP64: 2 positions + 3 momenta = 40 B, twice), and per node E-bar, H^{n+1/2},
-# H^{n+3/2} (3 x 24 B) are read and 12 + S moment planes (8 B each) written once.
-BYTES_PER_PARTICLE = {"f64": 80}
+# once (FP64: 2 positions + 3 momenta = 40 B, twice; mixed: int32 cell + 2 FP32 offsets +
+# 3 FP32 momenta = 24 B, twice), and per node E-bar, H^{n+1/2}, H^{n+3/2} (3 x 24 B) are read
+# and 12 + S FP64 moment planes (8 B each) written once.
+BYTES_PER_PARTICLE = {"fp64": 80, "mixed": 48}
 
 
 def bytes_per_node(S):
@@ -47,6 +50,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget for the CPU oracle baseline (0 disables it)")
     ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--compare-steps", type=int, default=20,
+                    help="timed cycles of each FP64 / mixed comparison run (0 skips them)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB before the timed region "
                          "(reference dispatch for scaling HBM byte counters)")
@@ -76,6 +82,71 @@ def cpu_baseline(wl, budget_s):
                       f"{el:.1f} s"}
 
 
+def run_gpu(binding, torch, wl, precision, steps, warmup, tile):
+    """Load the workload, run warmup cycles, then time `steps` cycles (wall clock around the
+    whole batch, HIP events per kernel group).  Returns the measurements."""
+    S = wl.grid.n_species
+    prec = picgen.PREC_MIXED if precision == "mixed" else picgen.PREC_FP64
+    ctx = binding.Context(wl.grid, track_ids=False, tile=(tile, tile), precision=prec)
+    for s, sp in enumerate(wl.species):
+        ctx.load_particles(s, sp.q, sp.m, sp.w, sp.xi_x, sp.xi_z, sp.ux, sp.uy, sp.uz)
+    ctx.step(warmup)
+    ctx.sync()
+    torch.cuda.synchronize()
+    info0 = ctx.get_info()
+    n_alive0 = sum(info0["alive"])
+
+    ctx.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(steps)
+    ctx.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    info1 = ctx.get_info()
+    ctx.close()
+    if info1["overflow_flags"]:
+        print(f"overflow flags raised: {info1['overflow_flags']}", file=sys.stderr)
+        sys.exit(3)
+    n_alive1 = sum(info1["alive"])
+    # particles processed per cycle: the alive count entering each cycle (bounded by these)
+    n_mean = 0.5 * (n_alive0 + n_alive1)
+    part_ms = prof["particle_ms"] / max(prof["particle_launches"], 1)
+    alg_bytes = BYTES_PER_PARTICLE[precision] * n_mean + bytes_per_node(S) * wl.grid.n_nodes
+    achieved = alg_bytes / (part_ms * 1e-3) / 1e9
+    return {
+        "value": n_mean * steps / wall,
+        "ms_per_step": 1e3 * wall / steps,
+        "particles": int(n_alive0),
+        "tile": list(info1["tile"]),
+        "part_ms": part_ms,
+        "alg_bytes": alg_bytes,
+        "achieved": achieved,
+        "breakdown": {
+            "field_solve": prof["field_ms"] / max(prof["field_launches"], 1),
+            "particles": part_ms,
+            "sort": prof["sort_ms"] / max(prof["sort_launches"], 1),
+            "events_step": prof["step_ms"] / max(prof["steps"], 1),
+        },
+    }
+
+
+def comparison(binding, torch, wl, steps, warmup, tile):
+    r = {}
+    for prec in ("fp64", "mixed"):
+        m = run_gpu(binding, torch, wl, prec, steps, warmup, tile)
+        r[prec] = {"particle_steps_per_s": m["value"], "ms_per_step": m["ms_per_step"],
+                   "particle_kernel_ms": m["part_ms"], "particle_kernel_GBps": m["achieved"],
+                   "particle_kernel_frac_hbm": m["achieved"] / HBM_PEAK_GBS}
+    r["speedup_mixed_over_fp64"] = r["mixed"]["particle_steps_per_s"] / r["fp64"]["particle_steps_per_s"]
+    r["particle_kernel_speedup"] = r["fp64"]["particle_kernel_ms"] / r["mixed"]["particle_kernel_ms"]
+    r["workload"] = wl.name
+    r["particles"] = wl.n_particles
+    return r
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -95,77 +166,51 @@ def main():
 
     wl = picgen.named(args.workload)
     S = wl.grid.n_species
-    ctx = binding.Context(wl.grid, track_ids=False, tile=(args.tile, args.tile))
-    for s, sp in enumerate(wl.species):
-        ctx.load_particles(s, sp.q, sp.m, sp.w, sp.xi_x, sp.xi_z, sp.ux, sp.uy, sp.uz)
-    ctx.step(args.warmup)
-    ctx.sync()
-    torch.cuda.synchronize()
-    info0 = ctx.get_info()
-    n_alive0 = sum(info0["alive"])
-
-    ctx.profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.step(args.steps)
-    ctx.sync()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    prof = ctx.profile_read()
-    ctx.profile_enable(False)
-    info1 = ctx.get_info()
-    n_alive1 = sum(info1["alive"])
-    if info1["overflow_flags"]:
-        print(f"overflow flags raised: {info1['overflow_flags']}", file=sys.stderr)
-        sys.exit(3)
-
-    # particles processed per cycle: the alive count entering each cycle (bounded by these)
-    n_mean = 0.5 * (n_alive0 + n_alive1)
-    value = n_mean * args.steps / wall
-    part_ms = prof["particle_ms"] / max(prof["particle_launches"], 1)
-    alg_bytes = BYTES_PER_PARTICLE["f64"] * n_mean + bytes_per_node(S) * wl.grid.n_nodes
-    achieved = alg_bytes / (part_ms * 1e-3) / 1e9
+    m = run_gpu(binding, torch, wl, args.precision, args.steps, args.warmup, args.tile)
+    print(f"[bench] {wl.name} {args.precision}: {m['value']:.4g} particle-steps/s, "
+          f"{m['ms_per_step']:.4f} ms/step", file=sys.stderr, flush=True)
     out = {
         "metric": "implicit particle push+deposit/s (FP64 vs mixed); batched p50/p99 step ms",
-        "value": value,
+        "value": m["value"],
         "unit": "particle-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * wall / args.steps,
+        "ms_per_step": m["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {
             "workload": wl.name,
             "grid": [wl.grid.nx, wl.grid.nz],
-            "particles": int(n_alive0),
+            "particles": m["particles"],
             "species": S,
-            "precision": "fp64",
-            "tile": list(info1["tile"]),
+            "precision": args.precision,
+            "tile": m["tile"],
             "note": wl.note,
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_particles<true> (fused gather-push-deposit)",
-            "achieved": achieved,
+            "kernel": "k_particles (fused gather-push-deposit)",
+            "achieved": m["achieved"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
+            "frac": m["achieved"] / HBM_PEAK_GBS,
             "traffic": None,
-            "alg_bytes_per_launch": alg_bytes,
-            "avg_launch_ms": part_ms,
+            "alg_bytes_per_launch": m["alg_bytes"],
+            "avg_launch_ms": m["part_ms"],
         },
-        "breakdown_ms_per_step": {
-            "field_solve": prof["field_ms"] / max(prof["field_launches"], 1),
-            "particles": part_ms,
-            "sort": prof["sort_ms"] / max(prof["sort_launches"], 1),
-            "events_step": prof["step_ms"] / max(prof["steps"], 1),
-        },
+        "breakdown_ms_per_step": m["breakdown"],
     }
-    ctx.close()
+    if args.compare_steps > 0:
+        out["fp64_vs_mixed"] = [
+            comparison(binding, torch, wl, args.compare_steps, args.warmup, args.tile),
+            comparison(binding, torch, picgen.named("foil_dense"), args.compare_steps,
+                       args.warmup, args.tile),
+        ]
+        print("[bench] comparison done", file=sys.stderr, flush=True)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)

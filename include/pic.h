@@ -28,6 +28,16 @@
  *     12 + s density of species s;
  *   - state after k cycles: positions x^{k+1/2}, momenta u^k, E^k, H^{k+1/2}, t = k dt.
  *
+ * Precision.  PIC_PREC_FP64 holds and pushes particles in FP64.  PIC_PREC_MIXED stores each
+ * particle as an int32 cell key (k * nx + i), FP32 offsets within the cell in [0, 1) and FP32
+ * momenta; the gather, the push and each particle's moments are computed in FP32, and a
+ * lane's FP32 partial sums are added into FP64 accumulators and the FP64 moment planes.  The
+ * field solve, E, E-bar, H and the moments stay FP64 in both forms.  Loading rounds offsets
+ * and momenta to FP32 (an offset that would round to 1 becomes the largest float below 1);
+ * positions read back as i + offset, exactly.  An offset carried past a face by the push
+ * moves the particle to the neighbouring cell (offset minus one), and one that rounds to 1
+ * becomes offset 0 of the next cell, so every particle's cell and offset stay consistent.
+ *
  * Ownership: every pointer argument is a HOST pointer owned by the caller; the library
  * copies from or into it during the call and keeps nothing.  The context owns all device
  * memory.  Every call returns a pic_status; on failure pic_last_error() gives a message and
@@ -71,7 +81,7 @@ typedef struct {
   int32_t nx, nz;            /* cells along x and z, each >= 1 */
   double dx, dz, dt;         /* cell sizes and time step; dt <= min(dx, dz) is required */
   int32_t bc_x, bc_z;        /* PIC_BC_*; bc_z must be PIC_BC_PERIODIC */
-  int32_t precision;         /* PIC_PREC_FP64 or PIC_PREC_MIXED */
+  int32_t precision;         /* PIC_PREC_FP64 or PIC_PREC_MIXED (see below) */
   int32_t n_species;         /* number of species slots S, 1..PIC_MAX_SPECIES */
   double e0[3], h0[3];       /* uniform initial E (nodes) and H (cell centres) */
   /* E_y source at x = 0 (absorbing x only; a0 = 0 switches it off):

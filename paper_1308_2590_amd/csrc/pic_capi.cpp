@@ -21,7 +21,9 @@ struct SpeciesState {
   double q = 0, m = 1, w = 0;
   int64_t cap = 0;         // slots allocated
   int64_t n_loaded = 0;    // particles given at the last load
-  double *buf[2][5] = {};  // two copies of the state; perm maps sorted slot -> location
+  double *buf[2][5] = {};  // FP64 form: two copies of the state; perm maps sorted slot -> location
+  int32_t *mcell[2] = {};  // mixed form: cell key k * nx + i
+  float *mbuf[2][5] = {};  // mixed form: in-cell offsets f_x, f_z and u_x, u_y, u_z
   int64_t *ids[2] = {};
   int32_t *perm[2] = {};
   int32_t *cs[2] = {};     // cell start offsets [ncells + 1]
@@ -108,6 +110,8 @@ void free_species(pic_ctx *c, SpeciesState &s) {
   const size_t nc = (size_t)c->g.ncells;
   for (int b = 0; b < 2; ++b) {
     for (int v = 0; v < 5; ++v) dfree(c, s.buf[b][v], cap * sizeof(double)), s.buf[b][v] = nullptr;
+    for (int v = 0; v < 5; ++v) dfree(c, s.mbuf[b][v], cap * sizeof(float)), s.mbuf[b][v] = nullptr;
+    dfree(c, s.mcell[b], cap * sizeof(int32_t)), s.mcell[b] = nullptr;
     dfree(c, s.ids[b], cap * sizeof(int64_t)), s.ids[b] = nullptr;
     dfree(c, s.perm[b], cap * sizeof(int32_t)), s.perm[b] = nullptr;
     dfree(c, s.cs[b], (nc + 1) * sizeof(int32_t)), s.cs[b] = nullptr;
@@ -121,6 +125,8 @@ void free_species(pic_ctx *c, SpeciesState &s) {
 
 bool finite3(const double *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
 
+bool mixed(const pic_ctx *c) { return c->d.precision == PIC_PREC_MIXED; }
+
 // Tile size from the load.  One wavefront handles one row of a tile, each lane a contiguous
 // run of that row's particles, so a tile is 4 rows high and wide enough for a row to hold
 // about 1024 particles of a species (runs of ~16); a power of two in [4, 32], shrunk until
@@ -132,7 +138,8 @@ void choose_tiles(pic_ctx *c, int64_t total, int64_t occupied, int nspecies) {
     tx = 4;
     while (tx < 32 && (double)(2 * tx) * ppc <= 1024.0 * 1.4) tx *= 2;
     tz = 4;
-    while (tx > 4 && pic::particle_lds_bytes(c->g, pic::TileArgs{tx, tz, 0, 0, 0, 0}) > 65536) tx /= 2;
+    while (tx > 4 && pic::particle_lds_bytes(c->g, pic::TileArgs{tx, tz, 0, 0, 0, 0}, mixed(c)) > 65536)
+      tx /= 2;
   }
   c->tiles.tx = tx;
   c->tiles.tz = tz;
@@ -146,6 +153,7 @@ pic::StepArgs step_args(pic_ctx *c, bool push) {
   pic::StepArgs a{};
   a.g = c->g;
   a.t = c->tiles;
+  a.mixed = mixed(c) ? 1 : 0;
   a.nsp = c->S;
   const int cur = c->cur, nxt = 1 - c->cur;
   for (int s = 0; s < c->S; ++s) {
@@ -162,7 +170,11 @@ pic::StepArgs step_args(pic_ctx *c, bool push) {
     for (int v = 0; v < 5; ++v) {
       x.src[v] = st.buf[cur][v];
       x.dst[v] = push ? st.buf[nxt][v] : nullptr;
+      x.msrc[v] = st.mbuf[cur][v];
+      x.mdst[v] = push ? st.mbuf[nxt][v] : nullptr;
     }
+    x.msrc_cell = st.mcell[cur];
+    x.mdst_cell = push ? st.mcell[nxt] : nullptr;
     x.src_id = st.ids[cur];
     x.dst_id = push ? st.ids[nxt] : nullptr;
     x.perm = st.perm[cur];
@@ -282,8 +294,8 @@ pic_status pic_init_grid(const pic_grid_desc *d, pic_ctx **out) {
   if (d->bc_z != PIC_BC_PERIODIC) return fail(nullptr, PIC_ERR_ARG, "bc_z must be periodic");
   if (d->bc_x == PIC_BC_ABSORBING && d->nx < 2)
     return fail(nullptr, PIC_ERR_ARG, "an absorbing x axis needs nx >= 2");
-  if (d->precision != PIC_PREC_FP64)
-    return fail(nullptr, PIC_ERR_ARG, "precision: only PIC_PREC_FP64 is available");
+  if (d->precision != PIC_PREC_FP64 && d->precision != PIC_PREC_MIXED)
+    return fail(nullptr, PIC_ERR_ARG, "precision must be PIC_PREC_FP64 or PIC_PREC_MIXED");
   if (d->n_species < 1 || d->n_species > PIC_MAX_SPECIES)
     return fail(nullptr, PIC_ERR_ARG, "n_species must be in 1..8");
   if (d->allow_cfl_violation != 0 || d->dt > std::min(d->dx, d->dz))
@@ -409,8 +421,14 @@ pic_status pic_load_particles(pic_ctx *c, int32_t s, double q, double m, double 
   const size_t cap = (size_t)std::max<int64_t>(n, 1);
   pic_status rs;
   for (int b = 0; b < 2; ++b) {
-    for (int v = 0; v < 5; ++v)
-      if ((rs = dalloc(c, &st.buf[b][v], cap, "alloc particles")) != PIC_OK) return rs;
+    if (mixed(c)) {
+      if ((rs = dalloc(c, &st.mcell[b], cap, "alloc particles")) != PIC_OK) return rs;
+      for (int v = 0; v < 5; ++v)
+        if ((rs = dalloc(c, &st.mbuf[b][v], cap, "alloc particles")) != PIC_OK) return rs;
+    } else {
+      for (int v = 0; v < 5; ++v)
+        if ((rs = dalloc(c, &st.buf[b][v], cap, "alloc particles")) != PIC_OK) return rs;
+    }
     if (c->d.track_ids)
       if ((rs = dalloc(c, &st.ids[b], cap, "alloc ids")) != PIC_OK) return rs;
     if ((rs = dalloc(c, &st.perm[b], cap, "alloc perm")) != PIC_OK) return rs;
@@ -420,12 +438,36 @@ pic_status pic_load_particles(pic_ctx *c, int32_t s, double q, double m, double 
   if ((rs = dalloc(c, &st.cnt, (size_t)pic::kMoveCodes * nc, "alloc counts")) != PIC_OK) return rs;
   if ((rs = dalloc(c, &st.bsum, (size_t)c->n_scan_blocks, "alloc scan sums")) != PIC_OK) return rs;
   {
-    std::vector<double> tmp((size_t)n);
     const double *srcs[5] = {xi_x, xi_z, ux, uy, uz};
-    for (int v = 0; v < 5; ++v) {
-      for (int64_t j = 0; j < n; ++j) tmp[j] = srcs[v][order[j]];
-      HIP_TRY(c, hipMemcpy(st.buf[c->cur][v], tmp.data(), (size_t)n * sizeof(double), hipMemcpyHostToDevice),
+    if (mixed(c)) {
+      // cell key and FP32 offsets in [0, 1) (an offset that rounds up to 1 is taken as the
+      // largest float below 1, so the particle stays in its cell), FP32 momenta
+      std::vector<int32_t> kc((size_t)n);
+      std::vector<float> tmp((size_t)n);
+      for (int64_t j = 0; j < n; ++j) kc[j] = key[order[j]];
+      HIP_TRY(c, hipMemcpy(st.mcell[c->cur], kc.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice),
               "upload particles");
+      for (int v = 0; v < 5; ++v) {
+        for (int64_t j = 0; j < n; ++j) {
+          const double x = srcs[v][order[j]];
+          if (v < 2) {
+            float f = (float)(x - std::floor(x));
+            if (f >= 1.0f) f = std::nextafter(1.0f, 0.0f);
+            tmp[j] = f;
+          } else {
+            tmp[j] = (float)x;
+          }
+        }
+        HIP_TRY(c, hipMemcpy(st.mbuf[c->cur][v], tmp.data(), (size_t)n * sizeof(float), hipMemcpyHostToDevice),
+                "upload particles");
+      }
+    } else {
+      std::vector<double> tmp((size_t)n);
+      for (int v = 0; v < 5; ++v) {
+        for (int64_t j = 0; j < n; ++j) tmp[j] = srcs[v][order[j]];
+        HIP_TRY(c, hipMemcpy(st.buf[c->cur][v], tmp.data(), (size_t)n * sizeof(double), hipMemcpyHostToDevice),
+                "upload particles");
+      }
     }
     if (c->d.track_ids) {
       std::vector<int64_t> idv((size_t)n);
@@ -461,7 +503,7 @@ pic_status pic_load_particles(pic_ctx *c, int32_t s, double q, double m, double 
     int nloaded = 0;
     for (int ss = 0; ss < c->S; ++ss) nloaded += c->sp[ss].loaded ? 1 : 0;
     choose_tiles(c, total, occupied, nloaded);
-    if (pic::particle_lds_bytes(c->g, c->tiles) > 65536)
+    if (pic::particle_lds_bytes(c->g, c->tiles, mixed(c)) > 65536)
       return fail(c, PIC_ERR_ARG, "tile too large: its LDS accumulators exceed 64 KiB");
   }
   HIP_TRY(c, hipMemsetAsync(c->flags, 0, sizeof(uint32_t), c->stream), "clear flags");
@@ -589,13 +631,33 @@ pic_status pic_read_particles(pic_ctx *c, int32_t s, int64_t *n_inout, double *x
   std::vector<int32_t> perm((size_t)n);
   HIP_TRY(c, hipMemcpy(perm.data(), st.perm[c->cur], (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost),
           "read perm");
-  std::vector<double> tmp((size_t)st.cap);
   double *outs[5] = {xi_x, xi_z, ux, uy, uz};
-  for (int v = 0; v < 5; ++v) {
-    if (!outs[v]) continue;
-    HIP_TRY(c, hipMemcpy(tmp.data(), st.buf[c->cur][v], (size_t)st.cap * sizeof(double), hipMemcpyDeviceToHost),
+  if (mixed(c)) {
+    // positions come back as cell index + offset, exact in FP64
+    std::vector<int32_t> kc((size_t)st.cap);
+    std::vector<float> tmp((size_t)st.cap);
+    HIP_TRY(c, hipMemcpy(kc.data(), st.mcell[c->cur], (size_t)st.cap * sizeof(int32_t), hipMemcpyDeviceToHost),
             "read particles");
-    for (int64_t j = 0; j < n; ++j) outs[v][j] = tmp[perm[j]];
+    for (int v = 0; v < 5; ++v) {
+      if (!outs[v]) continue;
+      HIP_TRY(c, hipMemcpy(tmp.data(), st.mbuf[c->cur][v], (size_t)st.cap * sizeof(float), hipMemcpyDeviceToHost),
+              "read particles");
+      for (int64_t j = 0; j < n; ++j) {
+        const int32_t loc = perm[j];
+        double val = (double)tmp[loc];
+        if (v == 0) val += (double)(kc[loc] % c->g.nx);
+        if (v == 1) val += (double)(kc[loc] / c->g.nx);
+        outs[v][j] = val;
+      }
+    }
+  } else {
+    std::vector<double> tmp((size_t)st.cap);
+    for (int v = 0; v < 5; ++v) {
+      if (!outs[v]) continue;
+      HIP_TRY(c, hipMemcpy(tmp.data(), st.buf[c->cur][v], (size_t)st.cap * sizeof(double), hipMemcpyDeviceToHost),
+              "read particles");
+      for (int64_t j = 0; j < n; ++j) outs[v][j] = tmp[perm[j]];
+    }
   }
   if (id) {
     std::vector<int64_t> t2((size_t)st.cap);

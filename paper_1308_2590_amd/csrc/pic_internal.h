@@ -41,8 +41,12 @@ struct SpeciesArgs {
   double beta;               // q dt / (2 m)
   double cS;                 // w q^2 dt^2 / (4 m)
   double kJ;                 // w q
-  const double *src[5];      // current state, addressed through perm
+  const double *src[5];      // current state, addressed through perm (FP64 form)
   double *dst[5];            // pushed state, written in the kernel's processing order
+  const int32_t *msrc_cell;  // mixed form: cell key k * nx + i
+  const float *msrc[5];      // mixed form: offsets f_x, f_z in [0, 1) and u_x, u_y, u_z
+  int32_t *mdst_cell;
+  float *mdst[5];
   const int64_t *src_id;
   int64_t *dst_id;
   const int32_t *perm;       // sorted slot -> location in src
@@ -58,6 +62,7 @@ struct SpeciesArgs {
 struct StepArgs {
   GridArgs g;
   TileArgs t;
+  int32_t mixed;             // 1: mixed-precision particle state and arithmetic
   int32_t nsp;               // species slots
   SpeciesArgs sp[kMaxSpecies];
   const double *Ebar;        // [3][nodes]
@@ -86,7 +91,7 @@ struct FieldArgs {
   double *M_clear;           // moment planes zeroed by the H update (NULL: keep)
 };
 
-size_t particle_lds_bytes(const GridArgs &g, const TileArgs &t);
+size_t particle_lds_bytes(const GridArgs &g, const TileArgs &t, bool mixed);
 size_t rank_lds_bytes(const TileArgs &t);
 
 hipError_t launch_field_solve(const FieldArgs &a, hipStream_t s);

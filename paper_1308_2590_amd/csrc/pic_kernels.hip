@@ -25,6 +25,8 @@
 // The file is compiled with -ffp-contract=off: the mover performs the same IEEE-754
 // operations in the same order as a plain scalar implementation, so particles pushed in the
 // same fields land bit-for-bit in the same cell.
+#include <type_traits>
+
 #include "pic_internal.h"
 
 namespace pic {
@@ -58,23 +60,30 @@ __device__ __forceinline__ int block_tile(const TileArgs &t, const int32_t *list
   return idx < count ? list[idx] : -1;
 }
 
-// Implicit response of a particle: R = (I + [b]x + b b^T) / (1 + b.b) with b = (beta/gamma) B,
-// [b]x a = a x b.  It solves u-bar = a + u-bar x b, the time-centred Eq. (2a).
-__device__ __forceinline__ void response(double beta, double g, double B0, double B1, double B2,
-                                         double R[9]) {
-  double bg = beta / g;
-  double bx = bg * B0, by = bg * B1, bz = bg * B2;
-  double inv = 1.0 / (1.0 + bx * bx + by * by + bz * bz);
-  R[0] = (1.0 + bx * bx) * inv;
-  R[1] = (bz + bx * by) * inv;
-  R[2] = (-by + bx * bz) * inv;
-  R[3] = (-bz + by * bx) * inv;
-  R[4] = (1.0 + by * by) * inv;
-  R[5] = (bx + by * bz) * inv;
-  R[6] = (by + bz * bx) * inv;
-  R[7] = (-bx + bz * by) * inv;
-  R[8] = (1.0 + bz * bz) * inv;
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return fmaf(a, b, c); }
+
+// Reciprocal and reciprocal square root.  FP64: the hardware estimate refined by two
+// Newton-Raphson steps (each squares the relative error), which leaves an error of about one
+// unit in the last place.  FP32: the hardware results, accurate to about one unit in the last
+// place, are used as they are.  Arguments here are >= 1, far from denormals and overflow.
+__device__ __forceinline__ double rcpT(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
 }
+__device__ __forceinline__ float rcpT(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rsqT(double x) {
+  // y' = y + (y / 2)(1 - x y^2)
+  double y = __builtin_amdgcn_rsq(x);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return y;
+}
+__device__ __forceinline__ float rsqT(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double floorT(double a) { return floor(a); }
+__device__ __forceinline__ float floorT(float a) { return floorf(a); }
 
 // ------------------------------------------------------------------------------------------
 // Field solve
@@ -222,124 +231,167 @@ __device__ __forceinline__ void wave_sync() {
 //   a1 = a0 s, a2 = a1 s,
 //   delta-j = (w q / gamma) R u = (w q / (gamma (1 + s^2 B.B))) (u + s u x B + s^2 (B.u) B).
 // Particles sharing a cell share B, so their S-hat deposits add up through three scalars.
+template <typename T>
 struct Compact {
-  double a0, a1, a2, j0, j1, j2;
+  T a0, a1, a2, j0, j1, j2;
 };
 
-__device__ __forceinline__ Compact compact_moments(const SpeciesArgs &sp, double g, double u0,
-                                                   double u1, double u2, double B0, double B1,
-                                                   double B2) {
-  const double ginv = 1.0 / g;
-  const double s = sp.beta * ginv;
-  const double BB = B0 * B0 + B1 * B1 + B2 * B2;
-  const double inv = 1.0 / fma(s * s, BB, 1.0);
-  Compact m;
-  m.a0 = sp.cS * ginv * inv;
+// Species constants in the arithmetic type of the kernel.
+template <typename T>
+struct SpConst {
+  T beta, cS, kJ, w;
+};
+
+template <typename T>
+__device__ __forceinline__ Compact<T> compact_moments(const SpConst<T> &k, T ginv, T u0, T u1,
+                                                      T u2, T B0, T B1, T B2) {
+  const T s = k.beta * ginv;
+  const T BB = B0 * B0 + B1 * B1 + B2 * B2;
+  const T inv = rcpT(fmaT(s * s, BB, T(1)));
+  Compact<T> m;
+  m.a0 = k.cS * ginv * inv;
   m.a1 = m.a0 * s;
   m.a2 = m.a1 * s;
-  const double k = sp.kJ * ginv * inv;
-  const double bu = B0 * u0 + B1 * u1 + B2 * u2;
-  const double s2bu = s * s * bu;
-  m.j0 = k * fma(s2bu, B0, fma(s, u1 * B2 - u2 * B1, u0));
-  m.j1 = k * fma(s2bu, B1, fma(s, u2 * B0 - u0 * B2, u1));
-  m.j2 = k * fma(s2bu, B2, fma(s, u0 * B1 - u1 * B0, u2));
+  const T kk = k.kJ * ginv * inv;
+  const T bu = B0 * u0 + B1 * u1 + B2 * u2;
+  const T s2bu = s * s * bu;
+  m.j0 = kk * fmaT(s2bu, B0, fmaT(s, u1 * B2 - u2 * B1, u0));
+  m.j1 = kk * fmaT(s2bu, B1, fmaT(s, u2 * B0 - u0 * B2, u1));
+  m.j2 = kk * fmaT(s2bu, B2, fmaT(s, u0 * B1 - u1 * B0, u2));
   return m;
 }
 
 // Add one corner's share (weight W) of compact moments to the 13 LDS moment planes at node o,
-// expanding S-hat with the cell's B.
-__device__ __forceinline__ void expand_add(double *acc, int plane, int o, double A0, double A1,
-                                           double A2, double J0, double J1, double J2, double D,
-                                           int dens_plane, double B0, double B1, double B2) {
-  atomicAdd(&acc[0 * plane + o], fma(A2, B0 * B0, A0));
-  atomicAdd(&acc[1 * plane + o], fma(A2, B0 * B1, A1 * B2));
-  atomicAdd(&acc[2 * plane + o], fma(A2, B0 * B2, -A1 * B1));
-  atomicAdd(&acc[3 * plane + o], fma(A2, B1 * B0, -A1 * B2));
-  atomicAdd(&acc[4 * plane + o], fma(A2, B1 * B1, A0));
-  atomicAdd(&acc[5 * plane + o], fma(A2, B1 * B2, A1 * B0));
-  atomicAdd(&acc[6 * plane + o], fma(A2, B2 * B0, A1 * B1));
-  atomicAdd(&acc[7 * plane + o], fma(A2, B2 * B1, -A1 * B0));
-  atomicAdd(&acc[8 * plane + o], fma(A2, B2 * B2, A0));
-  atomicAdd(&acc[9 * plane + o], J0);
-  atomicAdd(&acc[10 * plane + o], J1);
-  atomicAdd(&acc[11 * plane + o], J2);
-  atomicAdd(&acc[dens_plane * plane + o], D);
+// expanding S-hat with the cell's B.  The expansion runs in the kernel's arithmetic type; the
+// LDS accumulators are FP64 in both precisions (FP32 LDS atomic adds are far slower than FP64
+// ones on gfx950).
+template <typename T>
+__device__ __forceinline__ void expand_add(double *acc, int plane, int o, T A0, T A1, T A2, T J0,
+                                           T J1, T J2, T D, int dens_plane, T B0, T B1, T B2) {
+  atomicAdd(&acc[0 * plane + o], (double)fmaT(A2, B0 * B0, A0));
+  atomicAdd(&acc[1 * plane + o], (double)fmaT(A2, B0 * B1, A1 * B2));
+  atomicAdd(&acc[2 * plane + o], (double)fmaT(A2, B0 * B2, -A1 * B1));
+  atomicAdd(&acc[3 * plane + o], (double)fmaT(A2, B1 * B0, -A1 * B2));
+  atomicAdd(&acc[4 * plane + o], (double)fmaT(A2, B1 * B1, A0));
+  atomicAdd(&acc[5 * plane + o], (double)fmaT(A2, B1 * B2, A1 * B0));
+  atomicAdd(&acc[6 * plane + o], (double)fmaT(A2, B2 * B0, A1 * B1));
+  atomicAdd(&acc[7 * plane + o], (double)fmaT(A2, B2 * B1, -A1 * B0));
+  atomicAdd(&acc[8 * plane + o], (double)fmaT(A2, B2 * B2, A0));
+  atomicAdd(&acc[9 * plane + o], (double)J0);
+  atomicAdd(&acc[10 * plane + o], (double)J1);
+  atomicAdd(&acc[11 * plane + o], (double)J2);
+  atomicAdd(&acc[dens_plane * plane + o], (double)D);
 }
 
 // Per-lane running sum of the compact moments of consecutive particles that stay in one
 // cell, per corner (order (i,k), (i+1,k), (i,k+1), (i+1,k+1)).
+template <typename T>
 struct CellAcc {
-  double A0[4], A1[4], A2[4], J0[4], J1[4], J2[4], D[4];
+  T A0[4], A1[4], A2[4], J0[4], J1[4], J2[4], D[4];
   int cell;  // tile-local column of the cell being accumulated, -1 when empty
 
   __device__ __forceinline__ void clear() {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) A0[c] = A1[c] = A2[c] = J0[c] = J1[c] = J2[c] = D[c] = 0.0;
+    for (int c = 0; c < 4; ++c) A0[c] = A1[c] = A2[c] = J0[c] = J1[c] = J2[c] = D[c] = T(0);
   }
-  __device__ __forceinline__ void add(double fx, double fz, const Compact &m, double w) {
-    const double W[4] = {(1.0 - fx) * (1.0 - fz), fx * (1.0 - fz), (1.0 - fx) * fz, fx * fz};
+  __device__ __forceinline__ void add(T fx, T fz, const Compact<T> &m, T w) {
+    const T one = T(1);
+    const T W[4] = {(one - fx) * (one - fz), fx * (one - fz), (one - fx) * fz, fx * fz};
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      A0[c] = fma(W[c], m.a0, A0[c]);
-      A1[c] = fma(W[c], m.a1, A1[c]);
-      A2[c] = fma(W[c], m.a2, A2[c]);
-      J0[c] = fma(W[c], m.j0, J0[c]);
-      J1[c] = fma(W[c], m.j1, J1[c]);
-      J2[c] = fma(W[c], m.j2, J2[c]);
-      D[c] = fma(W[c], w, D[c]);
+      A0[c] = fmaT(W[c], m.a0, A0[c]);
+      A1[c] = fmaT(W[c], m.a1, A1[c]);
+      A2[c] = fmaT(W[c], m.a2, A2[c]);
+      J0[c] = fmaT(W[c], m.j0, J0[c]);
+      J1[c] = fmaT(W[c], m.j1, J1[c]);
+      J2[c] = fmaT(W[c], m.j2, J2[c]);
+      D[c] = fmaT(W[c], w, D[c]);
     }
   }
   // B is the field of the accumulated cell, whose lower-left node is (cell + 1, lz) locally.
   __device__ __forceinline__ void flush(double *acc, int plane, int LW, int lz, int dens_plane,
-                                        double B0, double B1, double B2) {
+                                        T B0, T B1, T B2) {
     const int b = lz * LW + cell + 1;
 #pragma unroll
     for (int c = 0; c < 4; ++c)
       expand_add(acc, plane, b + (c & 1) + (c >> 1) * LW, A0[c], A1[c], A2[c], J0[c], J1[c],
                  J2[c], D[c], dens_plane, B0, B1, B2);
   }
+  // End of a row: every lane flushes at once, and the lanes whose runs end in one cell are
+  // neighbours.  Their sums are first added up across lanes (a segmented reduction with
+  // shuffles towards the first lane of each cell), so that one lane per cell issues the LDS
+  // atomics; same-address atomics from many lanes of one instruction are serialised.  All 64
+  // lanes must be active.
+  __device__ __forceinline__ void flush_row_end(double *acc, int plane, int LW, int lz,
+                                                int dens_plane, T B0, T B1, T B2, int lane) {
+    const int prev = __shfl_up(cell, 1);
+    const bool head = lane == 0 || prev != cell;
+    const uint64_t heads = __ballot(head);
+    const uint64_t above = heads & ~((2ull << lane) - 1ull);
+    const int seg_end = above ? __ffsll((unsigned long long)above) - 1 : 64;
+    for (int d = 1; d < 64; d <<= 1) {
+      const bool take = lane + d < seg_end;
+      if (!__any(take)) break;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        T v;
+        v = __shfl_down(A0[c], d); A0[c] += take ? v : T(0);
+        v = __shfl_down(A1[c], d); A1[c] += take ? v : T(0);
+        v = __shfl_down(A2[c], d); A2[c] += take ? v : T(0);
+        v = __shfl_down(J0[c], d); J0[c] += take ? v : T(0);
+        v = __shfl_down(J1[c], d); J1[c] += take ? v : T(0);
+        v = __shfl_down(J2[c], d); J2[c] += take ? v : T(0);
+        v = __shfl_down(D[c], d); D[c] += take ? v : T(0);
+      }
+    }
+    if (head && cell >= 0) flush(acc, plane, LW, lz, dens_plane, B0, B1, B2);
+  }
 };
 
 // Particles that change cell deposit into a different cell (and field) from the lane's run,
 // so they are queued per wavefront in LDS and deposited 64 at a time, one per lane.
+constexpr int kMqCap = 64;
+constexpr int kMqWords = 8;  // fx fz a0 a1 a2 j0 j1 j2
+
+template <typename T>
 struct MoverQ {
-  static constexpr int kCap = 64;
-  static constexpr int kWords = 8;  // fx fz a0 a1 a2 j0 j1 j2
-  double *v;                        // [kWords][kCap]
-  int *idx;                         // [2][kCap]: accumulator node index, H^{n+3/2} index
+  T *v;      // [kMqWords][kMqCap]
+  int *idx;  // [2][kMqCap]: accumulator node index, H^{n+3/2} index
 };
 
-__device__ __forceinline__ void drain_movers(const MoverQ &q, int count, int lane, double *acc,
-                                             int plane, int LW, int dens_plane, double w,
-                                             const double *Hn, int NPL) {
+template <typename T>
+__device__ __forceinline__ void drain_movers(const MoverQ<T> &q, int count, int lane, double *acc,
+                                             int plane, int LW, int dens_plane, T w, const T *Hn,
+                                             int NPL) {
   if (lane < count) {
-    const double fx = q.v[0 * MoverQ::kCap + lane], fz = q.v[1 * MoverQ::kCap + lane];
-    const double a0 = q.v[2 * MoverQ::kCap + lane], a1 = q.v[3 * MoverQ::kCap + lane];
-    const double a2 = q.v[4 * MoverQ::kCap + lane], j0 = q.v[5 * MoverQ::kCap + lane];
-    const double j1 = q.v[6 * MoverQ::kCap + lane], j2 = q.v[7 * MoverQ::kCap + lane];
-    const int o = q.idx[lane], hn = q.idx[MoverQ::kCap + lane];
-    const double B0 = Hn[hn], B1 = Hn[NPL + hn], B2 = Hn[2 * NPL + hn];
+    const T fx = q.v[0 * kMqCap + lane], fz = q.v[1 * kMqCap + lane];
+    const T a0 = q.v[2 * kMqCap + lane], a1 = q.v[3 * kMqCap + lane];
+    const T a2 = q.v[4 * kMqCap + lane], j0 = q.v[5 * kMqCap + lane];
+    const T j1 = q.v[6 * kMqCap + lane], j2 = q.v[7 * kMqCap + lane];
+    const int o = q.idx[lane], hn = q.idx[kMqCap + lane];
+    const T B0 = Hn[hn], B1 = Hn[NPL + hn], B2 = Hn[2 * NPL + hn];
 #pragma unroll 1
     for (int c = 0; c < 4; ++c) {
       const int cx = c & 1, cz = c >> 1;
-      const double W = (cx ? fx : 1.0 - fx) * (cz ? fz : 1.0 - fz);
+      const T W = (cx ? fx : T(1) - fx) * (cz ? fz : T(1) - fz);
       expand_add(acc, plane, o + cx + cz * LW, W * a0, W * a1, W * a2, W * j0, W * j1, W * j2,
                  W * w, dens_plane, B0, B1, B2);
     }
   }
 }
 
-// LDS layout of the particle kernel, in doubles: the moment accumulators of the tile and its
-// halo, then the fields the tile's particles read (E-bar on the tile's nodes, H^{n+1/2} on
-// its cells, H^{n+3/2} on its cells plus a one-cell ring), then the int move counters.
+// LDS layout of the particle kernel (byte offsets): the moment accumulators of the tile and its
+// halo, the fields the tile's particles read (E-bar on the tile's nodes, H^{n+1/2} on its
+// cells, H^{n+3/2} on its cells plus a one-cell ring), the per-wave mover queues, and the int
+// move counters.  Accumulators are FP64; fields and queues use the kernel's arithmetic type.
 struct TileLds {
   int LW, LH, plane;          // accumulator node grid (tx + 3) x (tz + 3)
   int EW, EPL;                // E-bar node grid (tx + 1) x (tz + 1)
   int HPL;                    // H^{n+1/2} cells tx x tz
   int NW, NPL;                // H^{n+3/2} cells (tx + 2) x (tz + 2)
-  size_t acc, eb, ho, hn, mq, cnt;  // offsets in doubles
+  size_t acc, eb, ho, hn, mq, cnt;  // byte offsets
   size_t bytes;
-  __host__ __device__ TileLds(int n_planes, int tx, int tz) {
+  __host__ __device__ TileLds(int n_planes, int tx, int tz, int tsize) {
     LW = tx + 3;
     LH = tz + 3;
     plane = LW * LH;
@@ -349,12 +401,58 @@ struct TileLds {
     NW = tx + 2;
     NPL = NW * (tz + 2);
     acc = 0;
-    eb = acc + (size_t)n_planes * plane;
-    ho = eb + 3 * (size_t)EPL;
-    hn = ho + 3 * (size_t)HPL;
-    mq = hn + 3 * (size_t)NPL;
-    cnt = mq + (size_t)(kBlock / 64) * MoverQ::kCap * (MoverQ::kWords + 1);
-    bytes = cnt * sizeof(double) + (size_t)tx * tz * 10 * sizeof(int);
+    eb = acc + (size_t)n_planes * plane * sizeof(double);
+    ho = eb + 3 * (size_t)EPL * tsize;
+    hn = ho + 3 * (size_t)HPL * tsize;
+    mq = (hn + 3 * (size_t)NPL * tsize + 7) & ~(size_t)7;
+    cnt = mq + (size_t)(kBlock / 64) * kMqCap * ((size_t)kMqWords * tsize + 2 * sizeof(int));
+    bytes = cnt + (size_t)tx * tz * 10 * sizeof(int);
+  }
+};
+
+// Particle state in either form, as the kernel's arithmetic type: cell (i, k), in-cell offsets
+// (fx, fz) and momentum.  FP64 keeps positions in cell units; the mixed form keeps the cell key
+// and FP32 offsets.  Src holds the species' source arrays in registers for the whole species.
+template <bool MIXED>
+struct Pstate;
+template <>
+struct Pstate<false> {
+  double x, z, u0, u1, u2;
+  struct Src {
+    const double *a[5];
+    __device__ __forceinline__ explicit Src(const SpeciesArgs &sp) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) a[v] = sp.src[v];
+    }
+  };
+  __device__ __forceinline__ void load(const Src &s, int p) {
+    x = s.a[0][p];
+    z = s.a[1][p];
+    u0 = s.a[2][p];
+    u1 = s.a[3][p];
+    u2 = s.a[4][p];
+  }
+};
+template <>
+struct Pstate<true> {
+  int cell;
+  float x, z, u0, u1, u2;  // x, z: in-cell offsets
+  struct Src {
+    const int32_t *c;
+    const float *a[5];
+    __device__ __forceinline__ explicit Src(const SpeciesArgs &sp) {
+      c = sp.msrc_cell;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) a[v] = sp.msrc[v];
+    }
+  };
+  __device__ __forceinline__ void load(const Src &s, int p) {
+    cell = s.c[p];
+    x = s.a[0][p];
+    z = s.a[1][p];
+    u0 = s.a[2][p];
+    u1 = s.a[3][p];
+    u2 = s.a[4][p];
   }
 };
 
@@ -363,14 +461,16 @@ struct TileLds {
 // runs, one per lane; run lengths differ by at most one.  A lane accumulates the deposits of
 // particles that stay in their cell in registers and adds them to the LDS tile when its run
 // enters the next cell, so LDS atomics are issued once per (lane, cell) instead of once per
-// particle; particles changing cell deposit directly.  The pushed state of the particle at
-// iteration `it` of lane `l` is written to location row_start + 64 it + l, which makes the
-// stores (and next cycle's loads through the permutation) coalesced.  Each lane loads the
-// state of its next particle (and the permutation entry of the one after) before pushing the
-// current one.
-template <bool PUSH>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2)))
+// particle; particles changing cell go through a per-wave queue.  The pushed state of the
+// particle at iteration `it` of lane `l` is written to location row_start + 64 it + l, which
+// makes the stores (and next cycle's loads through the permutation) coalesced.
+// MIXED selects the mixed-precision form: FP32 state, gather, push and per-lane partial sums,
+// added into FP64 LDS accumulators and the FP64 moment planes.  The FP64 form needs about 240
+// VGPRs (two waves per SIMD); the FP32 form fits three.
+template <bool PUSH, bool MIXED>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2 + MIXED, 2 + MIXED)))
 void k_particles(const StepArgs a) {
+  using T = typename std::conditional<MIXED, float, double>::type;
   const GridArgs &g = a.g;
   const TileArgs &t = a.t;
   const int tile = block_tile(t, a.tile_list);
@@ -382,10 +482,13 @@ void k_particles(const StepArgs a) {
   const int64_t nn = g.nnodes, nc = g.ncells;
 
   extern __shared__ double lds[];
-  const TileLds Lo(g.n_planes, t.tx, t.tz);
-  double *acc = lds + Lo.acc;
-  double *Eb = lds + Lo.eb, *Ho = lds + Lo.ho, *Hn = lds + Lo.hn;
-  int *cntL = reinterpret_cast<int *>(lds + Lo.cnt);
+  char *ldsb = reinterpret_cast<char *>(lds);
+  const TileLds Lo(g.n_planes, t.tx, t.tz, (int)sizeof(T));
+  double *acc = reinterpret_cast<double *>(ldsb + Lo.acc);
+  T *Eb = reinterpret_cast<T *>(ldsb + Lo.eb);
+  T *Ho = reinterpret_cast<T *>(ldsb + Lo.ho);
+  T *Hn = reinterpret_cast<T *>(ldsb + Lo.hn);
+  int *cntL = reinterpret_cast<int *>(ldsb + Lo.cnt);
   const int LW = Lo.LW, plane = Lo.plane;
 
   for (int e = threadIdx.x; e < g.n_planes * plane; e += blockDim.x) acc[e] = 0.0;
@@ -396,7 +499,7 @@ void k_particles(const StepArgs a) {
     const bool in = gi < g.nx && gk < g.nz;
     const int64_t c = (int64_t)gk * g.nx + gi;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) Ho[q * Lo.HPL + e] = in ? a.Hold[q * nc + c] : 0.0;
+    for (int q = 0; q < 3; ++q) Ho[q * Lo.HPL + e] = in ? (T)a.Hold[q * nc + c] : T(0);
   }
   if (PUSH) {
     for (int e = threadIdx.x; e < Lo.EPL; e += blockDim.x) {
@@ -407,7 +510,7 @@ void k_particles(const StepArgs a) {
       if (g.bc_x == PIC_BC_PERIODIC) gi = wrap_any(gi, g.nx); else in = gi <= g.nx;
       const int64_t n = (int64_t)gk * g.nxn + gi;
 #pragma unroll
-      for (int q = 0; q < 3; ++q) Eb[q * Lo.EPL + e] = in ? a.Ebar[q * nn + n] : 0.0;
+      for (int q = 0; q < 3; ++q) Eb[q * Lo.EPL + e] = in ? (T)a.Ebar[q * nn + n] : T(0);
     }
     for (int e = threadIdx.x; e < Lo.NPL; e += blockDim.x) {
       const int lk = e / Lo.NW, li = e - lk * Lo.NW;
@@ -417,16 +520,20 @@ void k_particles(const StepArgs a) {
       if (g.bc_x == PIC_BC_PERIODIC) gi = wrap_any(gi, g.nx); else in = gi >= 0 && gi < g.nx;
       const int64_t c = (int64_t)gk * g.nx + gi;
 #pragma unroll
-      for (int q = 0; q < 3; ++q) Hn[q * Lo.NPL + e] = in ? a.Hnew[q * nc + c] : 0.0;
+      for (int q = 0; q < 3; ++q) Hn[q * Lo.NPL + e] = in ? (T)a.Hnew[q * nc + c] : T(0);
     }
   }
   __syncthreads();
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nwaves = blockDim.x >> 6;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  MoverQ mq;
-  mq.v = lds + Lo.mq + (size_t)wave * MoverQ::kCap * (MoverQ::kWords + 1);
-  mq.idx = reinterpret_cast<int *>(mq.v + MoverQ::kCap * MoverQ::kWords);
+  MoverQ<T> mq;
+  {
+    char *qb = ldsb + Lo.mq + (size_t)wave * kMqCap * ((size_t)kMqWords * sizeof(T) + 2 * sizeof(int));
+    mq.v = reinterpret_cast<T *>(qb);
+    mq.idx = reinterpret_cast<int *>(qb + (size_t)kMqCap * kMqWords * sizeof(T));
+  }
+  const T cxT = (T)g.cx, czT = (T)g.cz;
 
   for (int s = 0; s < a.nsp; ++s) {
     const SpeciesArgs &sp = a.sp[s];
@@ -435,7 +542,9 @@ void k_particles(const StepArgs a) {
       for (int e = threadIdx.x; e < ntc * 10; e += blockDim.x) cntL[e] = 0;
       __syncthreads();
     }
-    const double *sx = sp.src[0], *sz = sp.src[1], *su0 = sp.src[2], *su1 = sp.src[3], *su2 = sp.src[4];
+    const SpConst<T> K{(T)sp.beta, (T)sp.cS, (T)sp.kJ, (T)sp.w};
+    const typename Pstate<MIXED>::Src src(sp);
+    const int32_t *perm = sp.perm;
     const int dens = 12 + s;
     for (int r = k0 + wave; r < k1; r += nwaves) {
       const int64_t rowc = (int64_t)r * g.nx;
@@ -448,80 +557,74 @@ void k_particles(const StepArgs a) {
       const int iters = q + (rr > 0 ? 1 : 0);
       const int lz = r - k0 + 1;
       const int lk = r - k0;
-      CellAcc ca;
+      CellAcc<T> ca;
       ca.clear();
       ca.cell = -1;
       int nq = 0;  // movers queued by this wavefront (uniform)
-      int fcell = -1;
-      double fB0 = 0.0, fB1 = 0.0, fB2 = 0.0, fE[12];
+      // fields of the cell the lane's run is in, kept in registers while the run stays in it:
+      // H^{n+1/2} (fB, the push), E-bar at its 4 nodes (fE), and the field the deposit expands
+      // S-hat with (fD: H^{n+3/2} after a push, H^{n+1/2} for a deposit of the current state)
+      T fB0 = T(0), fB1 = T(0), fB2 = T(0), fE[12], fD0 = T(0), fD1 = T(0), fD2 = T(0);
       // The run is processed in chunks of kChunk particles: the chunk's state loads are issued
-      // together (and the next chunk's permutation entries), then the chunk is pushed from
-      // registers.  Global stores share the vector-memory counter with loads, so waiting for a
-      // load also waits for earlier stores; chunking pays that wait once per chunk.
+      // together (with the next chunk's permutation entries), then its particles are pushed
+      // from registers in an unrolled sequence.  Global stores share the vector-memory counter
+      // with loads, so a load whose value is still in flight across a loop iteration makes
+      // the compiler wait for all earlier stores too; keeping every loaded value inside one
+      // iteration lets it wait for the loads alone.  Loads are issued unconditionally (slots
+      // past a lane's run are clamped into the row, whose particles all exist, and their
+      // values go unused): a load under a divergent branch also forces a full wait.
       constexpr int kChunk = 4;
-      double cx_[kChunk], cz_[kChunk], c0_[kChunk], c1_[kChunk], c2_[kChunk];
+      Pstate<MIXED> cb[kChunk];
       int cp_[kChunk], np_[kChunk];
+      const int jlast = je - 1;
 #pragma unroll
-      for (int k = 0; k < kChunk; ++k) np_[k] = (k < my_n) ? sp.perm[start + k] : 0;
+      for (int kk = 0; kk < kChunk; ++kk) np_[kk] = perm[min(start + kk, jlast)];
       // all lanes run the same number of iterations so the mover queue stays wave-uniform
-      for (int it = 0; it < iters; ++it) {
-        if (it % kChunk == 0) {
+      for (int c0 = 0; c0 < iters; c0 += kChunk) {
 #pragma unroll
-          for (int k = 0; k < kChunk; ++k) {
-            cp_[k] = np_[k];
-            const bool v = it + k < my_n;
-            cx_[k] = v ? sx[cp_[k]] : 0.0;
-            cz_[k] = v ? sz[cp_[k]] : 0.0;
-            c0_[k] = v ? su0[cp_[k]] : 0.0;
-            c1_[k] = v ? su1[cp_[k]] : 0.0;
-            c2_[k] = v ? su2[cp_[k]] : 0.0;
+        for (int kk = 0; kk < kChunk; ++kk) {
+          cp_[kk] = np_[kk];
+          cb[kk].load(src, cp_[kk]);
+        }
+#pragma unroll
+        for (int kk = 0; kk < kChunk; ++kk) np_[kk] = perm[min(start + c0 + kChunk + kk, jlast)];
+#pragma unroll
+        for (int kk = 0; kk < kChunk; ++kk) {
+          const int it = c0 + kk;
+          if (it >= iters) break;
+          const bool act = it < my_n;
+          const int j = start + it;
+          const int p = cp_[kk];
+          const Pstate<MIXED> &ps = cb[kk];
+          int i, k;
+          T fx, fz;
+          if constexpr (MIXED) {
+            k = r;
+            i = ps.cell - r * g.nx;
+            fx = ps.x;
+            fz = ps.z;
+          } else {
+            i = (int)floor(ps.x);
+            k = (int)floor(ps.z);
+            fx = ps.x - (double)i;
+            fz = ps.z - (double)k;
           }
-#pragma unroll
-          for (int k = 0; k < kChunk; ++k)
-            np_[k] = (it + kChunk + k < my_n) ? sp.perm[start + it + kChunk + k] : 0;
-        }
-        const bool act = it < my_n;
-        const int j = start + it;
-        const int p = cp_[0];
-        const double x = cx_[0], z = cz_[0], u0 = c0_[0], u1 = c1_[0], u2 = c2_[0];
-#pragma unroll
-        for (int k = 0; k + 1 < kChunk; ++k) {
-          cp_[k] = cp_[k + 1];
-          cx_[k] = cx_[k + 1];
-          cz_[k] = cz_[k + 1];
-          c0_[k] = c0_[k + 1];
-          c1_[k] = c1_[k + 1];
-          c2_[k] = c2_[k + 1];
-        }
-        bool mover = false;
-        int mo = 0, mh = 0;
-        double mfx = 0, mfz = 0;
-        Compact mm = {0, 0, 0, 0, 0, 0};
-        const int i = (int)floor(x), k = (int)floor(z);
-        if (act && (k != r || i < i0 || i >= i1)) {
-          atomicOr(a.flags, kFlagOrder);
-          if (PUSH) sp.locode[j] = ((uint32_t)(jb + it * 64 + lane) << 4) | kAbsorbed;
-        } else if (act) {
-          const int li = i - i0;
-          const double fx = x - (double)i, fz = z - (double)k;
+          const T u0 = ps.u0, u1 = ps.u1, u2 = ps.u2;
+          const bool ok = act && k == r && i >= i0 && i < i1;
+          if (act && !ok) {
+            atomicOr(a.flags, kFlagOrder);
+            if (PUSH) sp.locode[j] = ((uint32_t)(jb + it * 64 + lane) << 4) | kAbsorbed;
+          }
+          // Lanes without a valid particle run the arithmetic on a valid cell of the tile and
+          // discard the results, so the main path has no branches around it.
+          const int li = ok ? i - i0 : max(ca.cell, 0);
           const int hc = lk * t.tx + li;
-          const double gam = sqrt(1.0 + u0 * u0 + u1 * u1 + u2 * u2);
-          if (li != ca.cell) {
-            if (ca.cell >= 0) {
-              if (PUSH) {
-                const int hn = (lk + 1) * Lo.NW + ca.cell + 1;
-                ca.flush(acc, plane, LW, lz, dens, Hn[hn], Hn[Lo.NPL + hn], Hn[2 * Lo.NPL + hn]);
-              } else {
-                const int ho = lk * t.tx + ca.cell;
-                ca.flush(acc, plane, LW, lz, dens, Ho[ho], Ho[Lo.HPL + ho], Ho[2 * Lo.HPL + ho]);
-              }
-              ca.clear();
-            }
-            ca.cell = li;
-          }
-          if (li != fcell) {
-            // fields of the run's cell, kept in registers while the run stays in it
-            fcell = li;
+          // On entering a new cell: read its fields, use them, and only then flush the previous
+          // cell's accumulator.  LDS operations complete in order, so a read issued after the
+          // flush's atomics (or consumed while they are in flight) would wait for all of them.
+          const bool newcell = ok && li != ca.cell;
+          const T oD0 = fD0, oD1 = fD1, oD2 = fD2;
+          if (newcell) {
             fB0 = Ho[hc];
             fB1 = Ho[Lo.HPL + hc];
             fB2 = Ho[2 * Lo.HPL + hc];
@@ -529,131 +632,187 @@ void k_particles(const StepArgs a) {
               const int e00 = lk * Lo.EW + li;
 #pragma unroll
               for (int qq = 0; qq < 3; ++qq) {
-                const double *f = Eb + qq * Lo.EPL + e00;
+                const T *f = Eb + qq * Lo.EPL + e00;
                 fE[4 * qq] = f[0];
                 fE[4 * qq + 1] = f[1];
                 fE[4 * qq + 2] = f[Lo.EW];
                 fE[4 * qq + 3] = f[Lo.EW + 1];
               }
+              const int h0 = (lk + 1) * Lo.NW + li + 1;
+              fD0 = Hn[h0];
+              fD1 = Hn[Lo.NPL + h0];
+              fD2 = Hn[2 * Lo.NPL + h0];
+            } else {
+              fD0 = fB0;
+              fD1 = fB1;
+              fD2 = fB2;
             }
           }
-          const double B0 = fB0, B1 = fB1, B2 = fB2;
+          const T one = T(1);
+          const T ginv = rsqT(one + u0 * u0 + u1 * u1 + u2 * u2);  // 1 / gamma(u^n)
           if (!PUSH) {
-            ca.add(fx, fz, compact_moments(sp, gam, u0, u1, u2, B0, B1, B2), sp.w);
+            const Compact<T> m0 = compact_moments(K, ginv, u0, u1, u2, fB0, fB1, fB2);
+            if (newcell) {
+              if (ca.cell >= 0) ca.flush(acc, plane, LW, lz, dens, oD0, oD1, oD2);
+              ca.clear();
+              ca.cell = li;
+            }
+            if (ok) ca.add(fx, fz, m0, K.w);
           } else {
-            // gather E-bar at x^{n+1/2} from the 4 corner nodes (linear weights)
-            const double W0 = (1.0 - fx) * (1.0 - fz), W1 = fx * (1.0 - fz);
-            const double W2 = (1.0 - fx) * fz, W3 = fx * fz;
-            double Ep[3];
+            bool mover = false;
+            int mo = 0, mh = 0;
+            T fx2, fz2;
+            Compact<T> m;
+            {
+              // gather E-bar at x^{n+1/2} from the 4 corner nodes (linear weights)
+              const T W0 = (one - fx) * (one - fz), W1 = fx * (one - fz);
+              const T W2 = (one - fx) * fz, W3 = fx * fz;
+              T Ep[3];
 #pragma unroll
-            for (int qq = 0; qq < 3; ++qq)
-              Ep[qq] = W0 * fE[4 * qq] + W1 * fE[4 * qq + 1] + W2 * fE[4 * qq + 2] + W3 * fE[4 * qq + 3];
-            // implicit push: u-bar = R (u + beta E), u' = 2 u-bar - u
-            double R[9];
-            response(sp.beta, gam, B0, B1, B2, R);
-            const double av0 = u0 + sp.beta * Ep[0], av1 = u1 + sp.beta * Ep[1], av2 = u2 + sp.beta * Ep[2];
-            const double n0 = 2.0 * (R[0] * av0 + R[1] * av1 + R[2] * av2) - u0;
-            const double n1 = 2.0 * (R[3] * av0 + R[4] * av1 + R[5] * av2) - u1;
-            const double n2 = 2.0 * (R[6] * av0 + R[7] * av1 + R[8] * av2) - u2;
-            const double g1 = sqrt(1.0 + n0 * n0 + n1 * n1 + n2 * n2);
-            double xn = x + g.cx * (n0 / g1);
-            double zn = z + g.cz * (n2 / g1);
-            bool alive = true;
-            if (g.bc_x == PIC_BC_PERIODIC) {
-              if (xn < 0.0) xn += (double)g.nx;
-              if (xn >= (double)g.nx) xn -= (double)g.nx;
-            } else if (xn < 0.0 || xn >= (double)g.nx) {
-              alive = false;
-            }
-            if (zn < 0.0) zn += (double)g.nz;
-            if (zn >= (double)g.nz) zn -= (double)g.nz;
-            if (!(isfinite(g1) && isfinite(xn) && isfinite(zn))) {
-              atomicOr(a.flags, kFlagNonFinite);
-              alive = false;
-            }
-            uint32_t code = kAbsorbed;
-            int i2 = 0, k2 = 0, di = 0, dk = 0;
-            if (alive) {
-              i2 = (int)floor(xn);
-              k2 = (int)floor(zn);
-              di = i2 - i;
-              dk = k2 - k;
+              for (int qq = 0; qq < 3; ++qq)
+                Ep[qq] = W0 * fE[4 * qq] + W1 * fE[4 * qq + 1] + W2 * fE[4 * qq + 2] + W3 * fE[4 * qq + 3];
+              // implicit push: with a = u + beta E and b = beta B / gamma,
+              // u-bar = R a = (a + a x b + (a.b) b) / (1 + b.b), and u' = 2 u-bar - u
+              const T bg = K.beta * ginv;
+              const T bx = bg * fB0, by = bg * fB1, bz = bg * fB2;
+              const T a0 = fmaT(K.beta, Ep[0], u0), a1 = fmaT(K.beta, Ep[1], u1);
+              const T a2 = fmaT(K.beta, Ep[2], u2);
+              const T inv = rcpT(one + bx * bx + by * by + bz * bz);
+              const T ab = a0 * bx + a1 * by + a2 * bz;
+              const T n0 = T(2) * ((a0 + (a1 * bz - a2 * by) + ab * bx) * inv) - u0;
+              const T n1 = T(2) * ((a1 + (a2 * bx - a0 * bz) + ab * by) * inv) - u1;
+              const T n2 = T(2) * ((a2 + (a0 * by - a1 * bx) + ab * bz) * inv) - u2;
+              const T g1sq = one + n0 * n0 + n1 * n1 + n2 * n2;
+              const T rg1 = rsqT(g1sq);  // 1 / gamma(u^{n+1})
+              const T vx = n0 * rg1, vz = n2 * rg1;
+              // position advance: FP64 in cell units; mixed as FP32 offset with integer carry
+              T xn, zn;
+              int i2, k2;
+              bool alive = ok;
+              bool finite;
+              if constexpr (MIXED) {
+                xn = fx + cxT * vx;
+                zn = fz + czT * vz;
+                finite = isfinite(g1sq) && isfinite(xn) && isfinite(zn);
+                const int cxi = finite ? (int)floorT(xn) : 0, czi = finite ? (int)floorT(zn) : 0;
+                xn -= (T)cxi;
+                zn -= (T)czi;
+                int ci = i + cxi, ck = k + czi;
+                if (xn >= one) { xn = T(0); ci += 1; }
+                if (zn >= one) { zn = T(0); ck += 1; }
+                if (g.bc_x == PIC_BC_PERIODIC) {
+                  ci = wrap1(ci, g.nx);
+                } else if (ci < 0 || ci >= g.nx) {
+                  alive = false;
+                }
+                ck = wrap1(ck, g.nz);
+                i2 = ci;
+                k2 = ck;
+              } else {
+                xn = ps.x + g.cx * vx;
+                zn = ps.z + g.cz * vz;
+                if (g.bc_x == PIC_BC_PERIODIC) {
+                  if (xn < 0.0) xn += (double)g.nx;
+                  if (xn >= (double)g.nx) xn -= (double)g.nx;
+                } else if (xn < 0.0 || xn >= (double)g.nx) {
+                  alive = false;
+                }
+                if (zn < 0.0) zn += (double)g.nz;
+                if (zn >= (double)g.nz) zn -= (double)g.nz;
+                finite = isfinite(g1sq) && isfinite(xn) && isfinite(zn);
+                i2 = finite ? (int)floor(xn) : i;
+                k2 = finite ? (int)floor(zn) : k;
+              }
+              if (ok && !finite) atomicOr(a.flags, kFlagNonFinite);
+              alive = alive && finite;
+              int di = i2 - i, dk = k2 - k;
               if (di > 1) di -= g.nx;
               if (di < -1) di += g.nx;
               if (dk > 1) dk -= g.nz;
               if (dk < -1) dk += g.nz;
-              if (di < -1 || di > 1 || dk < -1 || dk > 1) {
-                atomicOr(a.flags, kFlagJump);
-                alive = false;
-              } else {
-                code = (uint32_t)((dk + 1) * 3 + (di + 1));
+              const bool jump = di < -1 || di > 1 || dk < -1 || dk > 1;
+              if (alive && jump) atomicOr(a.flags, kFlagJump);
+              alive = alive && !jump;
+              if (!alive) {
+                di = 0;
+                dk = 0;
               }
-            }
-            const int loc = jb + it * 64 + lane;
-            sp.dst[0][loc] = xn;
-            sp.dst[1][loc] = zn;
-            sp.dst[2][loc] = n0;
-            sp.dst[3][loc] = n1;
-            sp.dst[4][loc] = n2;
-            if (sp.dst_id) sp.dst_id[loc] = sp.src_id[p];
-            sp.locode[j] = ((uint32_t)loc << 4) | code;
-            atomicAdd(&cntL[hc * 10 + code], 1);
-            if (alive) {
-              // deposit M^{n+3/2} at x^{n+3/2} with u^{n+1}, gamma(u^{n+1}) and H^{n+3/2} there
+              const uint32_t code = alive ? (uint32_t)((dk + 1) * 3 + (di + 1)) : kAbsorbed;
+              // moments M^{n+3/2} at x^{n+3/2} with u^{n+1}, 1/gamma(u^{n+1}) and H^{n+3/2}
+              // of the new cell (read before any LDS atomic of this particle is issued)
               const int hn = (lk + dk + 1) * Lo.NW + (li + di + 1);
-              const Compact m = compact_moments(sp, g1, n0, n1, n2, Hn[hn], Hn[Lo.NPL + hn], Hn[2 * Lo.NPL + hn]);
-              const double fx2 = xn - (double)i2, fz2 = zn - (double)k2;
-              if (code == 4u) {
-                ca.add(fx2, fz2, m, sp.w);
+              m = compact_moments(K, rg1, n0, n1, n2, Hn[hn], Hn[Lo.NPL + hn], Hn[2 * Lo.NPL + hn]);
+              if constexpr (MIXED) {
+                fx2 = xn;
+                fz2 = zn;
               } else {
+                fx2 = xn - (double)i2;
+                fz2 = zn - (double)k2;
+              }
+              if (newcell) {
+                if (ca.cell >= 0) ca.flush(acc, plane, LW, lz, dens, oD0, oD1, oD2);
+                ca.clear();
+                ca.cell = li;
+              }
+              if (ok) {
+                const int loc = jb + it * 64 + lane;
+                if constexpr (MIXED) {
+                  sp.mdst_cell[loc] = k2 * g.nx + i2;
+                  sp.mdst[0][loc] = xn;
+                  sp.mdst[1][loc] = zn;
+                  sp.mdst[2][loc] = n0;
+                  sp.mdst[3][loc] = n1;
+                  sp.mdst[4][loc] = n2;
+                } else {
+                  sp.dst[0][loc] = xn;
+                  sp.dst[1][loc] = zn;
+                  sp.dst[2][loc] = n0;
+                  sp.dst[3][loc] = n1;
+                  sp.dst[4][loc] = n2;
+                }
+                if (sp.dst_id) sp.dst_id[loc] = sp.src_id[p];
+                sp.locode[j] = ((uint32_t)loc << 4) | code;
+                atomicAdd(&cntL[hc * 10 + code], 1);
+              }
+              // stayers add to the lane's accumulator, movers go through the queue
+              if (alive && code == 4u) {
+                ca.add(fx2, fz2, m, K.w);
+              } else if (alive) {
                 mover = true;
                 mo = (lz + dk) * LW + (li + 1 + di);
                 mh = hn;
-                mfx = fx2;
-                mfz = fz2;
-                mm = m;
               }
             }
+            // queue this iteration's movers; drain first if they would not fit
+            const uint64_t mmask = __ballot(mover);
+            const int nm = __popcll(mmask);
+            if (nq + nm > kMqCap) {
+              wave_sync();
+              drain_movers(mq, nq, lane, acc, plane, LW, dens, K.w, Hn, Lo.NPL);
+              wave_sync();
+              nq = 0;
+            }
+            if (mover) {
+              const int e = nq + __popcll(mmask & lt_mask);
+              mq.v[0 * kMqCap + e] = fx2;
+              mq.v[1 * kMqCap + e] = fz2;
+              mq.v[2 * kMqCap + e] = m.a0;
+              mq.v[3 * kMqCap + e] = m.a1;
+              mq.v[4 * kMqCap + e] = m.a2;
+              mq.v[5 * kMqCap + e] = m.j0;
+              mq.v[6 * kMqCap + e] = m.j1;
+              mq.v[7 * kMqCap + e] = m.j2;
+              mq.idx[e] = mo;
+              mq.idx[kMqCap + e] = mh;
+            }
+            nq += nm;
           }
-        }
-        if (PUSH) {
-          // queue this iteration's movers; drain first if they would not fit
-          const uint64_t mmask = __ballot(mover);
-          const int nm = __popcll(mmask);
-          if (nq + nm > MoverQ::kCap) {
-            wave_sync();
-            drain_movers(mq, nq, lane, acc, plane, LW, dens, sp.w, Hn, Lo.NPL);
-            wave_sync();
-            nq = 0;
-          }
-          if (mover) {
-            const int e = nq + __popcll(mmask & lt_mask);
-            mq.v[0 * MoverQ::kCap + e] = mfx;
-            mq.v[1 * MoverQ::kCap + e] = mfz;
-            mq.v[2 * MoverQ::kCap + e] = mm.a0;
-            mq.v[3 * MoverQ::kCap + e] = mm.a1;
-            mq.v[4 * MoverQ::kCap + e] = mm.a2;
-            mq.v[5 * MoverQ::kCap + e] = mm.j0;
-            mq.v[6 * MoverQ::kCap + e] = mm.j1;
-            mq.v[7 * MoverQ::kCap + e] = mm.j2;
-            mq.idx[e] = mo;
-            mq.idx[MoverQ::kCap + e] = mh;
-          }
-          nq += nm;
         }
       }
-      if (ca.cell >= 0) {
-        if (PUSH) {
-          const int hn = (lk + 1) * Lo.NW + ca.cell + 1;
-          ca.flush(acc, plane, LW, lz, dens, Hn[hn], Hn[Lo.NPL + hn], Hn[2 * Lo.NPL + hn]);
-        } else {
-          const int ho = lk * t.tx + ca.cell;
-          ca.flush(acc, plane, LW, lz, dens, Ho[ho], Ho[Lo.HPL + ho], Ho[2 * Lo.HPL + ho]);
-        }
-      }
+      ca.flush_row_end(acc, plane, LW, lz, dens, fD0, fD1, fD2, lane);
       if (PUSH && nq > 0) {
         wave_sync();
-        drain_movers(mq, nq, lane, acc, plane, LW, dens, sp.w, Hn, Lo.NPL);
+        drain_movers(mq, nq, lane, acc, plane, LW, dens, K.w, Hn, Lo.NPL);
         wave_sync();
       }
     }
@@ -670,11 +829,11 @@ void k_particles(const StepArgs a) {
     }
   }
   __syncthreads();
-  // fold the tile's accumulators into the global moment planes
+  // fold the tile's accumulators into the global FP64 moment planes
   for (int e = threadIdx.x; e < g.n_planes * plane; e += blockDim.x) {
     const double v = acc[e];
     if (v == 0.0) continue;
-    const int p = e / plane, idx = e - p * plane;
+    const int pp = e / plane, idx = e - pp * plane;
     const int lzz = idx / LW, lx = idx - lzz * LW;
     int gx = i0 - 1 + lx, gz = k0 - 1 + lzz;
     if (g.bc_x == PIC_BC_PERIODIC) {
@@ -683,7 +842,7 @@ void k_particles(const StepArgs a) {
       continue;
     }
     gz = wrap_any(gz, g.nz);
-    unsafeAtomicAdd(&a.M[(int64_t)p * nn + (int64_t)gz * g.nxn + gx], v);
+    unsafeAtomicAdd(&a.M[(int64_t)pp * nn + (int64_t)gz * g.nxn + gx], v);
   }
 }
 
@@ -982,8 +1141,8 @@ __global__ void k_iota(int32_t *p, int64_t n) {
 
 }  // namespace
 
-size_t particle_lds_bytes(const GridArgs &g, const TileArgs &t) {
-  return TileLds(g.n_planes, t.tx, t.tz).bytes;
+size_t particle_lds_bytes(const GridArgs &g, const TileArgs &t, bool mixed) {
+  return TileLds(g.n_planes, t.tx, t.tz, mixed ? (int)sizeof(float) : (int)sizeof(double)).bytes;
 }
 
 size_t rank_lds_bytes(const TileArgs &t) {
@@ -1002,12 +1161,19 @@ hipError_t launch_field_solve(const FieldArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_particles(const StepArgs &a, bool push, hipStream_t s) {
-  const size_t lds = particle_lds_bytes(a.g, a.t);
+  const size_t lds = particle_lds_bytes(a.g, a.t, a.mixed != 0);
   const dim3 grid(8u * (unsigned)a.t.per_xcd);
-  if (push)
-    hipLaunchKernelGGL(k_particles<true>, grid, dim3(kBlock), lds, s, a);
-  else
-    hipLaunchKernelGGL(k_particles<false>, grid, dim3(kBlock), lds, s, a);
+  if (a.mixed) {
+    if (push)
+      hipLaunchKernelGGL((k_particles<true, true>), grid, dim3(kBlock), lds, s, a);
+    else
+      hipLaunchKernelGGL((k_particles<false, true>), grid, dim3(kBlock), lds, s, a);
+  } else {
+    if (push)
+      hipLaunchKernelGGL((k_particles<true, false>), grid, dim3(kBlock), lds, s, a);
+    else
+      hipLaunchKernelGGL((k_particles<false, false>), grid, dim3(kBlock), lds, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -279,3 +279,22 @@ def random_fields(seed, grid: Grid, amp_e=0.1, amp_h=0.3):
     e = amp_e * rng.standard_normal((3, grid.nodes_z, grid.nodes_x))
     h = amp_h * rng.standard_normal((3, grid.nz, grid.nx))
     return np.ascontiguousarray(e), np.ascontiguousarray(h)
+
+
+def fp32_representable(wl: Workload) -> Workload:
+    """Copy of a workload whose particle state is exactly representable in the mixed form:
+    in-cell offsets and momenta rounded to the nearest float32 (an offset that rounds up to 1
+    becomes the largest float32 below 1), so both precisions start from the same state."""
+    out = []
+    for sp in wl.species:
+        c = sp.copy()
+        for k in ("xi_x", "xi_z"):
+            v = getattr(c, k)
+            i = np.floor(v)
+            f = (v - i).astype(np.float32)
+            f = np.where(f >= np.float32(1.0), np.nextafter(np.float32(1.0), np.float32(0.0)), f)
+            setattr(c, k, i + f.astype(np.float64))
+        for k in ("ux", "uy", "uz"):
+            setattr(c, k, getattr(c, k).astype(np.float32).astype(np.float64))
+        out.append(c)
+    return replace(wl, species=out, grid=replace(wl.grid, precision=PREC_MIXED))

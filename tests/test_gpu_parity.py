@@ -172,10 +172,12 @@ def test_laser_source_and_absorbing_boundary(pic):
 
 
 @pytest.mark.parametrize("q,m", [(-1.0, 1.0), (2.0, 9.0)])
-def test_test_particles_bit_exact(pic, q, m):
+def test_test_particles_many_cycles(pic, q, m):
     """Zero-weight particles deposit nothing and uniform fields stay exactly uniform, so the
-    push runs in identical fields on both sides: positions, momenta and the sorted order must
-    agree bit for bit over many cycles (same IEEE operations in the same order)."""
+    push runs in identical fields on both sides and nothing chaotic amplifies the rounding
+    differences (the GPU evaluates the response in its vector form and uses refined
+    reciprocals): after 40 cycles positions and momenta agree to 1e-12 and the sorted order is
+    identical."""
     rng = np.random.default_rng(9)
     g = picgen.Grid(nx=24, nz=19, dx=0.8, dz=0.7, dt=0.5, n_species=1,
                     e0=(0.03, -0.05, 0.02), h0=(0.1, 0.4, -0.6))
@@ -188,11 +190,7 @@ def test_test_particles_bit_exact(pic, q, m):
     for _ in range(4):
         ctx.step(10)
         orc.step(10)
-        gp = ctx.read_particles(0)
-        op = orc.particles(0)
-        assert np.array_equal(gp["id"], op["id"])
-        for k in ("xi_x", "xi_z", "ux", "uy", "uz"):
-            assert np.array_equal(gp[k], op[k]), k
+        check_particles(ctx, orc, wl, tol=1e-12)
     ctx.close()
 
 
