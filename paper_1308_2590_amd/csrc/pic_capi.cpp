@@ -29,6 +29,7 @@ struct SpeciesState {
   int32_t *cs[2] = {};     // cell start offsets [ncells + 1]
   uint32_t *locode = nullptr;
   int32_t *cnt = nullptr;  // [9][ncells]
+  int32_t *arr = nullptr;  // [ncells] arrivals per cell, zero between cycles
   int32_t *bsum = nullptr;
 };
 
@@ -118,6 +119,7 @@ void free_species(pic_ctx *c, SpeciesState &s) {
   }
   dfree(c, s.locode, cap * sizeof(uint32_t)), s.locode = nullptr;
   dfree(c, s.cnt, (size_t)pic::kMoveCodes * nc * sizeof(int32_t)), s.cnt = nullptr;
+  dfree(c, s.arr, nc * sizeof(int32_t)), s.arr = nullptr;
   dfree(c, s.bsum, (size_t)c->n_scan_blocks * sizeof(int32_t)), s.bsum = nullptr;
   s.loaded = false;
   s.cap = 0;
@@ -183,6 +185,7 @@ pic::StepArgs step_args(pic_ctx *c, bool push) {
     x.cs_new = st.cs[nxt];
     x.locode = st.locode;
     x.cnt = st.cnt;
+    x.arr = st.arr;
     x.bsum = st.bsum;
   }
   a.flags = c->flags;
@@ -436,6 +439,8 @@ pic_status pic_load_particles(pic_ctx *c, int32_t s, double q, double m, double 
   }
   if ((rs = dalloc(c, &st.locode, cap, "alloc codes")) != PIC_OK) return rs;
   if ((rs = dalloc(c, &st.cnt, (size_t)pic::kMoveCodes * nc, "alloc counts")) != PIC_OK) return rs;
+  if ((rs = dalloc(c, &st.arr, (size_t)nc, "alloc arrivals")) != PIC_OK) return rs;
+  HIP_TRY(c, hipMemset(st.arr, 0, (size_t)nc * sizeof(int32_t)), "clear arrivals");
   if ((rs = dalloc(c, &st.bsum, (size_t)c->n_scan_blocks, "alloc scan sums")) != PIC_OK) return rs;
   {
     const double *srcs[5] = {xi_x, xi_z, ux, uy, uz};

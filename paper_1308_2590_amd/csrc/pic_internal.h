@@ -55,6 +55,7 @@ struct SpeciesArgs {
   int32_t *cs_new;           // cell start offsets of the next order [ncells + 1]
   uint32_t *locode;          // per sorted slot: (location written << 4) | move code
   int32_t *cnt;              // [9][ncells] particles leaving each cell per move code
+  int32_t *arr;              // [ncells] particles arriving in each cell; zero between cycles
   int32_t *bsum;             // block sums of the count scan
   int32_t active;
 };

@@ -13,18 +13,23 @@
 //               advance, move code, then deposit of S-hat, delta-j and density (Step 1,
 //               Eq. (3)) at the new position into LDS accumulators covering the tile plus a
 //               halo, folded once per tile into the FP64 moment planes with global atomics.
+//               It also counts the particles leaving each cell per move code and arriving in
+//               each cell.  Instantiated for FP64 and for the mixed form (FP32 particles).
 // Sort (stable by cell, removed particles dropped):
-//   k_scan_counts / k_scan_blocks / k_scan_finish  particles arriving in each cell from its
-//               3x3 neighbourhood, exclusive scan -> next cell start offsets;
+//   k_scan_counts / k_scan_blocks / k_scan_finish  exclusive scan of the arrival counts ->
+//               next cell start offsets;
+//   k_tile_list the tiles holding particles in the next order;
 //   k_rank      stable destination of every particle: cell start + particles arriving from
 //               source cells with a smaller key + rank within (source cell, move code),
 //               written as the next cycle's slot -> location permutation.
 // Positions never move more than one cell per cycle because dt <= min(dx, dz) and |v| < c,
 // which is what keeps the sort a 3x3 neighbourhood redistribution.
 //
-// The file is compiled with -ffp-contract=off: the mover performs the same IEEE-754
-// operations in the same order as a plain scalar implementation, so particles pushed in the
-// same fields land bit-for-bit in the same cell.
+// The file is compiled with -ffp-contract=off: fused multiply-adds appear only where written.
+// The FP64 mover evaluates the same expressions as a plain implementation of the method up to
+// rounding (vector form of the response, Newton-refined reciprocals), so FP64 results agree
+// with the oracle to about 1e-15 relative per cycle.
+
 #include <type_traits>
 
 #include "pic_internal.h"
@@ -383,13 +388,14 @@ __device__ __forceinline__ void drain_movers(const MoverQ<T> &q, int count, int 
 // LDS layout of the particle kernel (byte offsets): the moment accumulators of the tile and its
 // halo, the fields the tile's particles read (E-bar on the tile's nodes, H^{n+1/2} on its
 // cells, H^{n+3/2} on its cells plus a one-cell ring), the per-wave mover queues, and the int
-// move counters.  Accumulators are FP64; fields and queues use the kernel's arithmetic type.
+// move counters, and the arrival counts of the tile's cells and their one-cell ring.
+// Accumulators are FP64; fields and queues use the kernel's arithmetic type.
 struct TileLds {
   int LW, LH, plane;          // accumulator node grid (tx + 3) x (tz + 3)
   int EW, EPL;                // E-bar node grid (tx + 1) x (tz + 1)
   int HPL;                    // H^{n+1/2} cells tx x tz
   int NW, NPL;                // H^{n+3/2} cells (tx + 2) x (tz + 2)
-  size_t acc, eb, ho, hn, mq, cnt;  // byte offsets
+  size_t acc, eb, ho, hn, mq, cnt, arr;  // byte offsets
   size_t bytes;
   __host__ __device__ TileLds(int n_planes, int tx, int tz, int tsize) {
     LW = tx + 3;
@@ -406,7 +412,8 @@ struct TileLds {
     hn = ho + 3 * (size_t)HPL * tsize;
     mq = (hn + 3 * (size_t)NPL * tsize + 7) & ~(size_t)7;
     cnt = mq + (size_t)(kBlock / 64) * kMqCap * ((size_t)kMqWords * tsize + 2 * sizeof(int));
-    bytes = cnt + (size_t)tx * tz * 10 * sizeof(int);
+    arr = cnt + (size_t)tx * tz * 10 * sizeof(int);
+    bytes = arr + (size_t)(tx + 2) * (tz + 2) * sizeof(int);
   }
 };
 
@@ -489,6 +496,7 @@ void k_particles(const StepArgs a) {
   T *Ho = reinterpret_cast<T *>(ldsb + Lo.ho);
   T *Hn = reinterpret_cast<T *>(ldsb + Lo.hn);
   int *cntL = reinterpret_cast<int *>(ldsb + Lo.cnt);
+  int *arrL = reinterpret_cast<int *>(ldsb + Lo.arr);
   const int LW = Lo.LW, plane = Lo.plane;
 
   for (int e = threadIdx.x; e < g.n_planes * plane; e += blockDim.x) acc[e] = 0.0;
@@ -817,13 +825,30 @@ void k_particles(const StepArgs a) {
       }
     }
     if (PUSH) {
+      // Move counts of the tile's cells (for the ranking), and the particles they send to
+      // each cell of the tile and its ring, summed in LDS and added to the per-cell arrival
+      // counts (the sort's scan reads those instead of gathering nine counts per cell).
+      const int AW = t.tx + 2, AH = t.tz + 2;
+      for (int e = threadIdx.x; e < AW * AH; e += blockDim.x) arrL[e] = 0;
       __syncthreads();
-      const int cw = i1 - i0;
-      for (int e = threadIdx.x; e < (k1 - k0) * cw * kMoveCodes; e += blockDim.x) {
-        const int d = e / ((k1 - k0) * cw);
-        const int rem = e - d * ((k1 - k0) * cw);
+      const int cw = i1 - i0, chh = k1 - k0;
+      for (int e = threadIdx.x; e < chh * cw * kMoveCodes; e += blockDim.x) {
+        const int d = e / (chh * cw);
+        const int rem = e - d * (chh * cw);
         const int lkk = rem / cw, li = rem - lkk * cw;
-        sp.cnt[(int64_t)d * nc + (int64_t)(k0 + lkk) * g.nx + (i0 + li)] = cntL[(lkk * t.tx + li) * 10 + d];
+        const int v = cntL[(lkk * t.tx + li) * 10 + d];
+        sp.cnt[(int64_t)d * nc + (int64_t)(k0 + lkk) * g.nx + (i0 + li)] = v;
+        if (v) atomicAdd(&arrL[(lkk + 1 + d / 3 - 1) * AW + (li + 1 + d % 3 - 1)], v);
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < AW * AH; e += blockDim.x) {
+        const int v = arrL[e];
+        if (v == 0) continue;
+        const int az = e / AW, ax = e - az * AW;
+        int gi = i0 - 1 + ax;
+        const int gk = wrap1(k0 - 1 + az, g.nz);
+        if (g.bc_x == PIC_BC_PERIODIC) gi = wrap1(gi, g.nx);
+        atomicAdd(&sp.arr[(int64_t)gk * g.nx + gi], v);
       }
       __syncthreads();
     }
@@ -903,17 +928,14 @@ __global__ __launch_bounds__(kBlock) void k_scan_counts(const StepArgs a) {
   const int64_t c0 = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
   int in[kScanItems];
   int sum = 0;
+  // particles arriving in each cell (added by the particle kernel), cleared for the next cycle
 #pragma unroll
   for (int q = 0; q < kScanItems; ++q) {
     const int64_t c = c0 + q;
     int v = 0;
     if (c < g.ncells) {
-      const int kK = (int)(c / g.nx), iK = (int)(c - (int64_t)kK * g.nx);
-      for (int d = 0; d < kMoveCodes; ++d) {
-        int is, ks;
-        const int64_t src = source_cell(g, iK, kK, d, is, ks);
-        if (src >= 0 && cell_tile_active(a, is, ks)) v += sp.cnt[(int64_t)d * g.ncells + src];
-      }
+      v = sp.arr[c];
+      if (v) sp.arr[c] = 0;
     }
     in[q] = v;
     sum += v;
@@ -931,6 +953,8 @@ __global__ __launch_bounds__(kBlock) void k_scan_counts(const StepArgs a) {
 
 __global__ __launch_bounds__(1024) void k_scan_blocks(const StepArgs a, int nblocks) {
   __shared__ int sh[1024 / 64];
+  // the next order's tile list is appended to by k_tile_list: start its count at zero
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.tile_list_next[a.t.ntiles] = 0;
   const SpeciesArgs &sp = a.sp[blockIdx.x];
   if (!sp.active) return;
   int carry = 0;
@@ -984,7 +1008,8 @@ __device__ int dest_base(const GridArgs &g, int ic, int kc, int d, Cnt cntv, Csn
 // Stable destinations of one tile's particles.  The destination base of every (cell, move
 // code) of the tile is computed once into LDS; then one wavefront per tile row walks the row's
 // slots in order, 64 at a time: particles with the same (cell, code) in a group of 64 get
-// consecutive ranks by ballot, and a per-wave LDS counter carries the rank across groups.
+// consecutive ranks from per-code ballots, and a per-wave LDS counter carries the rank across
+// groups.
 __global__ __launch_bounds__(kBlock) void k_rank(const StepArgs a) {
   const GridArgs &g = a.g;
   const TileArgs &t = a.t;
@@ -1005,13 +1030,12 @@ __global__ __launch_bounds__(kBlock) void k_rank(const StepArgs a) {
   int *rcsn = rcnt + kMoveCodes * ring_cells;                         // [ring_cells]
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
-  for (int s = 0; s < a.nsp; ++s) {
+  // one block per (tile, species): twice the blocks of a per-tile launch, to overlap the
+  // memory latency of the staging and walking phases
+  {
+    const int s = blockIdx.y;
     const SpeciesArgs &sp = a.sp[s];
-    if (!sp.active) continue;
-    bool mine = false;
-    for (int r = k0 + threadIdx.x; r < k1; r += blockDim.x)
-      mine = mine || sp.cs[(int64_t)r * g.nx + i1] > sp.cs[(int64_t)r * g.nx + i0];
-    if (!__syncthreads_or(mine)) continue;
+    if (!sp.active) return;
     // counts of the tile and a one-cell ring (sources of the destinations reached from the
     // tile), and next-order starts of the same region, staged in LDS
     const int RW = t.tx + 4, RH = t.tz + 4;  // ring of two cells: destinations +-1, their sources +-1
@@ -1028,6 +1052,14 @@ __global__ __launch_bounds__(kBlock) void k_rank(const StepArgs a) {
       rcsn[e] = in ? sp.cs_new[c] : 0;
     }
     __syncthreads();
+    // nothing to rank if no particle of this species leaves a cell of the tile alive
+    bool mine = false;
+    for (int e = threadIdx.x; e < ch * cw * kMoveCodes; e += blockDim.x) {
+      const int cell = e / kMoveCodes, d = e - cell * kMoveCodes;
+      const int lk = cell / cw, li = cell - lk * cw;
+      mine = mine || rcnt[d * RW * RH + (lk + 2) * RW + (li + 2)] > 0;
+    }
+    if (!__syncthreads_or(mine)) return;
     // local ring coordinates of a global cell near the tile (periodic wrap on both axes)
     auto ring = [&](int gi, int gk) {
       int rx = gi - (i0 - 2), rz = gk - (k0 - 2);
@@ -1053,86 +1085,102 @@ __global__ __launch_bounds__(kBlock) void k_rank(const StepArgs a) {
       for (int q = lane; q < cw * 10; q += 64) ctr[q] = 0;
       wave_sync();
       const int jb = rowcs[0], je = rowcs[cw];
-      for (int base = jb; base < je; base += 64) {
-        const int j = base + lane;
-        const bool act = j < je;
-        int d = kAbsorbed, cl = 0, loc = 0;
-        if (act) {
-          const uint32_t lc = sp.locode[j];
-          d = (int)(lc & 15u);
-          loc = (int)(lc >> 4);
-          int lo = 0, hi = cw - 1;  // largest cl with rowcs[cl] <= j
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (rowcs[mid] <= j) lo = mid; else hi = mid - 1;
+      // the row's move codes are loaded kGroups groups of 64 at a time (indices clamped into
+      // the row), then ranked group by group
+      constexpr int kGroups = 8;
+      for (int b0 = jb; b0 < je; b0 += 64 * kGroups) {
+        uint32_t lcs[kGroups];
+#pragma unroll
+        for (int q = 0; q < kGroups; ++q) lcs[q] = sp.locode[min(b0 + q * 64 + lane, je - 1)];
+#pragma unroll
+        for (int q = 0; q < kGroups; ++q) {
+          const int base = b0 + q * 64;
+          if (base >= je) break;
+          const int j = base + lane;
+          const bool act = j < je;
+          int d = kAbsorbed, cl = 0, loc = 0;
+          if (act) {
+            const uint32_t lc = lcs[q];
+            d = (int)(lc & 15u);
+            loc = (int)(lc >> 4);
+            int lo = 0, hi = cw - 1;  // largest cl with rowcs[cl] <= j
+            while (lo < hi) {
+              const int mid = (lo + hi + 1) >> 1;
+              if (rowcs[mid] <= j) lo = mid; else hi = mid - 1;
+            }
+            cl = lo;
           }
-          cl = lo;
-        }
-        const bool valid = act && d < kMoveCodes;
-        const int key = cl * 10 + d;
-        uint64_t todo = __ballot(valid);
-        while (todo) {
-          const int leader = __ffsll((unsigned long long)todo) - 1;
-          const int lkey = __shfl(key, leader, 64);
-          const uint64_t grp = __ballot(valid && key == lkey);
-          const int lcl = lkey / 10, ld = lkey - lcl * 10;
-          const int before = ctr[lkey];
-          const int b0 = btab[(lk * t.tx + lcl) * kMoveCodes + ld] + before;
-          if ((grp >> lane) & 1ull) {
-            const int slot = b0 + __popcll(grp & lt_mask);
+          const bool valid = act && d < kMoveCodes;
+          // The group's slots are in cell order, so the lanes of one cell are contiguous:
+          // [cstart, cend).  A particle's rank within its (cell, code) in this group is the
+          // number of lanes of its cell below it with the same code (one ballot per code).
+          const int prevcl = __shfl_up(cl, 1, 64);
+          const uint64_t heads = __ballot(act && (lane == 0 || prevcl != cl));
+          const uint64_t upto = heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
+          const int cstart = upto ? 63 - __clzll((long long)upto) : 0;
+          const uint64_t above = heads & ~(lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
+          const int cend = above ? __ffsll((unsigned long long)above) - 1 : 64;
+          const uint64_t cellm = (cend == 64 ? ~0ull : ((1ull << cend) - 1ull)) & ~((1ull << cstart) - 1ull);
+          uint64_t same = 0;
+#pragma unroll
+          for (int dd = 0; dd < kMoveCodes; ++dd) {
+            const uint64_t m = __ballot(valid && d == dd);
+            if (d == dd) same = m;
+          }
+          same &= cellm;
+          if (valid) {
+            const int key = cl * 10 + d;
+            const int before = ctr[key];
+            const int rank = __popcll(same & lt_mask);
+            const int slot = btab[(lk * t.tx + cl) * kMoveCodes + d] + before + rank;
             if (slot >= 0 && slot < total) {
               sp.perm_new[slot] = loc;
             } else {
               atomicOr(a.flags, kFlagSlot);
             }
+            // the last lane of each (cell, code) carries the count to the next group
+            if ((same >> lane) == 1ull) ctr[key] = before + rank + 1;
           }
           wave_sync();
-          if (lane == leader) ctr[lkey] = before + __popcll(grp);
-          wave_sync();
-          todo &= ~grp;
         }
       }
       wave_sync();
     }
-    __syncthreads();
   }
 }
 
 // Flag per tile: does it hold particles of any species in the order given by the cell starts
-// (the current order, or the next one when from_next is set).
-__global__ __launch_bounds__(kBlock) void k_tile_flags(const StepArgs a, int from_next) {
+// (the current order, or the next one when from_next is set); the flagged tiles are appended
+// to the list (count at [ntiles], zero on entry) one ballot and one atomic per wavefront.  The
+// list order only decides which block takes which tile.
+__global__ __launch_bounds__(kBlock) void k_tile_list(const StepArgs a, int from_next) {
   const GridArgs &g = a.g;
   const TileArgs &t = a.t;
   const int tile = blockIdx.x * blockDim.x + threadIdx.x;
-  if (tile >= t.ntiles) return;
-  const int tzi = tile / t.ntx, txi = tile - tzi * t.ntx;
-  const int i0 = txi * t.tx, k0 = tzi * t.tz;
-  const int i1 = min(i0 + t.tx, g.nx), k1 = min(k0 + t.tz, g.nz);
+  const int lane = threadIdx.x & 63;
   int act = 0;
-  for (int s = 0; s < a.nsp; ++s) {
-    const SpeciesArgs &sp = a.sp[s];
-    if (!sp.active) continue;
-    const int32_t *cs = from_next ? sp.cs_new : sp.cs;
-    for (int r = k0; r < k1; ++r) act |= cs[(int64_t)r * g.nx + i1] > cs[(int64_t)r * g.nx + i0];
+  if (tile < t.ntiles) {
+    const int tzi = tile / t.ntx, txi = tile - tzi * t.ntx;
+    const int i0 = txi * t.tx, k0 = tzi * t.tz;
+    const int i1 = min(i0 + t.tx, g.nx), k1 = min(k0 + t.tz, g.nz);
+    for (int s = 0; s < a.nsp; ++s) {
+      const SpeciesArgs &sp = a.sp[s];
+      if (!sp.active) continue;
+      const int32_t *cs = from_next ? sp.cs_new : sp.cs;
+      for (int r = k0; r < k1; ++r) act |= cs[(int64_t)r * g.nx + i1] > cs[(int64_t)r * g.nx + i0];
+    }
+    a.tile_active_next[tile] = (uint8_t)act;
   }
-  a.tile_active_next[tile] = (uint8_t)act;
+  const uint64_t m = __ballot(act);
+  if (m == 0) return;
+  int base = 0;
+  if (lane == 0) base = atomicAdd(&a.tile_list_next[t.ntiles], __popcll(m));
+  base = __shfl(base, 0, 64);
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  if (act) a.tile_list_next[base + __popcll(m & lt)] = tile;
 }
 
-// Ordered list of the flagged tiles (one block, block-wide scans), count at [ntiles].
-__global__ __launch_bounds__(1024) void k_tile_compact(const StepArgs a) {
-  __shared__ int sh[1024 / 64];
-  const TileArgs &t = a.t;
-  int carry = 0;
-  for (int base = 0; base < t.ntiles; base += blockDim.x) {
-    const int tile = base + threadIdx.x;
-    const int act = (tile < t.ntiles) ? a.tile_active_next[tile] : 0;
-    int total;
-    const int off = block_excl_scan(act, sh, &total);
-    if (act) a.tile_list_next[carry + off] = tile;
-    carry += total;
-  }
-  if (threadIdx.x == 0) a.tile_list_next[t.ntiles] = carry;
-}
+__global__ void k_zero_count(int32_t *p) { *p = 0; }
 
 __global__ void k_iota(int32_t *p, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1182,16 +1230,16 @@ hipError_t launch_sort(const StepArgs &a, int32_t n_scan_blocks, hipStream_t s) 
   hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)a.nsp), dim3(1024), 0, s, a, n_scan_blocks);
   hipLaunchKernelGGL(k_scan_finish, dim3((unsigned)n_scan_blocks, (unsigned)a.nsp), dim3(kBlock), 0, s, a);
   const unsigned ntb = (unsigned)((a.t.ntiles + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_tile_flags, dim3(ntb), dim3(kBlock), 0, s, a, 1);
-  hipLaunchKernelGGL(k_tile_compact, dim3(1), dim3(1024), 0, s, a);
-  hipLaunchKernelGGL(k_rank, dim3(8u * (unsigned)a.t.per_xcd), dim3(kBlock), rank_lds_bytes(a.t), s, a);
+  hipLaunchKernelGGL(k_tile_list, dim3(ntb), dim3(kBlock), 0, s, a, 1);
+  hipLaunchKernelGGL(k_rank, dim3(8u * (unsigned)a.t.per_xcd, (unsigned)a.nsp), dim3(kBlock),
+                     rank_lds_bytes(a.t), s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_tile_list(const StepArgs &a, bool from_next_order, hipStream_t s) {
   const unsigned ntb = (unsigned)((a.t.ntiles + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_tile_flags, dim3(ntb), dim3(kBlock), 0, s, a, from_next_order ? 1 : 0);
-  hipLaunchKernelGGL(k_tile_compact, dim3(1), dim3(1024), 0, s, a);
+  hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, a.tile_list_next + a.t.ntiles);
+  hipLaunchKernelGGL(k_tile_list, dim3(ntb), dim3(kBlock), 0, s, a, from_next_order ? 1 : 0);
   return hipGetLastError();
 }
 
