@@ -18,7 +18,8 @@
 // Sort (stable by cell, removed particles dropped):
 //   k_scan_counts / k_scan_blocks / k_scan_finish  exclusive scan of the arrival counts ->
 //               next cell start offsets;
-//   k_tile_list the tiles holding particles in the next order;
+//   k_tile_flags / k_tile_compact  the tiles holding particles in the next order, as flags and
+//               as an ordered list;
 //   k_rank      stable destination of every particle: cell start + particles arriving from
 //               source cells with a smaller key + rank within (source cell, move code),
 //               written as the next cycle's slot -> location permutation.
@@ -953,8 +954,6 @@ __global__ __launch_bounds__(kBlock) void k_scan_counts(const StepArgs a) {
 
 __global__ __launch_bounds__(1024) void k_scan_blocks(const StepArgs a, int nblocks) {
   __shared__ int sh[1024 / 64];
-  // the next order's tile list is appended to by k_tile_list: start its count at zero
-  if (blockIdx.x == 0 && threadIdx.x == 0) a.tile_list_next[a.t.ntiles] = 0;
   const SpeciesArgs &sp = a.sp[blockIdx.x];
   if (!sp.active) return;
   int carry = 0;
@@ -1150,37 +1149,52 @@ __global__ __launch_bounds__(kBlock) void k_rank(const StepArgs a) {
 }
 
 // Flag per tile: does it hold particles of any species in the order given by the cell starts
-// (the current order, or the next one when from_next is set); the flagged tiles are appended
-// to the list (count at [ntiles], zero on entry) one ballot and one atomic per wavefront.  The
-// list order only decides which block takes which tile.
-__global__ __launch_bounds__(kBlock) void k_tile_list(const StepArgs a, int from_next) {
+// (the current order, or the next one when from_next is set).  One thread per tile.
+__global__ __launch_bounds__(kBlock) void k_tile_flags(const StepArgs a, int from_next) {
   const GridArgs &g = a.g;
   const TileArgs &t = a.t;
   const int tile = blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & 63;
+  if (tile >= t.ntiles) return;
+  const int tzi = tile / t.ntx, txi = tile - tzi * t.ntx;
+  const int i0 = txi * t.tx, k0 = tzi * t.tz;
+  const int i1 = min(i0 + t.tx, g.nx), k1 = min(k0 + t.tz, g.nz);
   int act = 0;
-  if (tile < t.ntiles) {
-    const int tzi = tile / t.ntx, txi = tile - tzi * t.ntx;
-    const int i0 = txi * t.tx, k0 = tzi * t.tz;
-    const int i1 = min(i0 + t.tx, g.nx), k1 = min(k0 + t.tz, g.nz);
-    for (int s = 0; s < a.nsp; ++s) {
-      const SpeciesArgs &sp = a.sp[s];
-      if (!sp.active) continue;
-      const int32_t *cs = from_next ? sp.cs_new : sp.cs;
-      for (int r = k0; r < k1; ++r) act |= cs[(int64_t)r * g.nx + i1] > cs[(int64_t)r * g.nx + i0];
-    }
-    a.tile_active_next[tile] = (uint8_t)act;
+  for (int s = 0; s < a.nsp; ++s) {
+    const SpeciesArgs &sp = a.sp[s];
+    if (!sp.active) continue;
+    const int32_t *cs = from_next ? sp.cs_new : sp.cs;
+    for (int r = k0; r < k1; ++r) act |= cs[(int64_t)r * g.nx + i1] > cs[(int64_t)r * g.nx + i0];
   }
-  const uint64_t m = __ballot(act);
-  if (m == 0) return;
-  int base = 0;
-  if (lane == 0) base = atomicAdd(&a.tile_list_next[t.ntiles], __popcll(m));
-  base = __shfl(base, 0, 64);
-  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  if (act) a.tile_list_next[base + __popcll(m & lt)] = tile;
+  a.tile_active_next[tile] = (uint8_t)act;
 }
 
-__global__ void k_zero_count(int32_t *p) { *p = 0; }
+// Ordered list of the flagged tiles, count at [ntiles].  One block; each thread takes a run of
+// kPer consecutive flags (loaded together), one block-wide scan per pass places the runs.  The
+// list order decides which block takes which tile: in tile order, the blocks of one XCD take
+// neighbouring tiles.
+__global__ __launch_bounds__(1024) void k_tile_compact(const StepArgs a) {
+  __shared__ int sh[1024 / 64];
+  constexpr int kPer = 16;
+  const int ntiles = a.t.ntiles;
+  int carry = 0;
+  for (int pbase = 0; pbase < ntiles; pbase += (int)blockDim.x * kPer) {
+    const int tb = pbase + (int)threadIdx.x * kPer;
+    uint8_t f[kPer];
+    int n = 0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      f[q] = (tb + q < ntiles) ? a.tile_active_next[tb + q] : (uint8_t)0;
+      n += f[q];
+    }
+    int total;
+    int pos = carry + block_excl_scan(n, sh, &total);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q)
+      if (f[q]) a.tile_list_next[pos++] = tb + q;
+    carry += total;
+  }
+  if (threadIdx.x == 0) a.tile_list_next[ntiles] = carry;
+}
 
 __global__ void k_iota(int32_t *p, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1230,7 +1244,8 @@ hipError_t launch_sort(const StepArgs &a, int32_t n_scan_blocks, hipStream_t s) 
   hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)a.nsp), dim3(1024), 0, s, a, n_scan_blocks);
   hipLaunchKernelGGL(k_scan_finish, dim3((unsigned)n_scan_blocks, (unsigned)a.nsp), dim3(kBlock), 0, s, a);
   const unsigned ntb = (unsigned)((a.t.ntiles + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_tile_list, dim3(ntb), dim3(kBlock), 0, s, a, 1);
+  hipLaunchKernelGGL(k_tile_flags, dim3(ntb), dim3(kBlock), 0, s, a, 1);
+  hipLaunchKernelGGL(k_tile_compact, dim3(1), dim3(1024), 0, s, a);
   hipLaunchKernelGGL(k_rank, dim3(8u * (unsigned)a.t.per_xcd, (unsigned)a.nsp), dim3(kBlock),
                      rank_lds_bytes(a.t), s, a);
   return hipGetLastError();
@@ -1238,8 +1253,8 @@ hipError_t launch_sort(const StepArgs &a, int32_t n_scan_blocks, hipStream_t s) 
 
 hipError_t launch_tile_list(const StepArgs &a, bool from_next_order, hipStream_t s) {
   const unsigned ntb = (unsigned)((a.t.ntiles + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, a.tile_list_next + a.t.ntiles);
-  hipLaunchKernelGGL(k_tile_list, dim3(ntb), dim3(kBlock), 0, s, a, from_next_order ? 1 : 0);
+  hipLaunchKernelGGL(k_tile_flags, dim3(ntb), dim3(kBlock), 0, s, a, from_next_order ? 1 : 0);
+  hipLaunchKernelGGL(k_tile_compact, dim3(1), dim3(1024), 0, s, a);
   return hipGetLastError();
 }
 
