@@ -178,8 +178,54 @@ pic_status pic_profile_read(pic_ctx *ctx, pic_profile *out);
 /* Message for the last failed call on this context (or of pic_init_grid when ctx is NULL). */
 const char *pic_last_error(const pic_ctx *ctx);
 
-/* Release the context and all its device memory.  NULL is allowed. */
+/* Release the context and all its device memory (removing it from its batch first).  NULL is
+ * allowed. */
 void pic_destroy(pic_ctx *ctx);
+
+/* ---- Batches: many independent runs stepped together ----------------------------------------
+ *
+ * A batch steps its member contexts with one launch of each kernel per cycle for all members
+ * together (persistent blocks over the work items of every member), optionally replaying a
+ * captured HIP graph of one cycle.  This is the same cycle as pic_step (Sec. 3.3), so each
+ * member's results are those of stepping it alone, up to the order of floating-point atomic
+ * additions.  Members keep their own device memory and stay readable (pic_read_*,
+ * pic_get_info) between batch steps; while in a batch they run on the batch's stream and
+ * pic_step / pic_set_stream on them return PIC_ERR_STATE.  Loading particles or fields into a
+ * member, or pic_set_step, is allowed and takes effect at the next batch step.  All members
+ * must be on the batch's device, use the batch's precision and have particles loaded. */
+typedef struct pic_batch pic_batch;
+
+/* Create an empty batch on a HIP device for contexts of the given precision (PIC_PREC_*).
+ * Errors: PIC_ERR_ARG, PIC_ERR_DEVICE. */
+pic_status pic_batch_create(int32_t device, int32_t precision, pic_batch **out);
+
+/* Add a context (PIC_ERR_ARG if it is NULL, already in a batch, on another device, of another
+ * precision, or has no particles) / remove it (PIC_ERR_ARG if it is not a member).  Removal
+ * waits for the batch's queued work and returns the context to its own stream. */
+pic_status pic_batch_add(pic_batch *b, pic_ctx *ctx);
+pic_status pic_batch_remove(pic_batch *b, pic_ctx *ctx);
+
+/* Advance every member nsteps cycles.  Work is queued on the batch's stream; the call returns
+ * without waiting.  An empty batch is a no-op.  Errors: PIC_ERR_ARG (nsteps < 0),
+ * PIC_ERR_DEVICE, PIC_ERR_OOM (growing the batch tables). */
+pic_status pic_batch_step(pic_batch *b, int32_t nsteps);
+
+/* on = 1: capture one cycle of all members in a HIP graph (again after every change of the
+ * membership or of a member's load) and replay it for each cycle; 0: launch the kernels
+ * directly (the default). */
+pic_status pic_batch_set_graph(pic_batch *b, int32_t on);
+
+/* Wait for the batch's queued work. */
+pic_status pic_batch_sync(pic_batch *b);
+
+/* Number of member contexts. */
+pic_status pic_batch_size(const pic_batch *b, int32_t *n);
+
+/* Message for the last failed call on this batch (or of pic_batch_create when b is NULL). */
+const char *pic_batch_last_error(const pic_batch *b);
+
+/* Release the batch (members are removed and stay valid).  NULL is allowed. */
+void pic_batch_destroy(pic_batch *b);
 
 #ifdef __cplusplus
 }

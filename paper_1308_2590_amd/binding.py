@@ -22,7 +22,10 @@ MAX_SPECIES = 8
 EXPORTED = ["pic_init_grid", "pic_load_particles", "pic_load_fields", "pic_set_step", "pic_step",
             "pic_read_moments", "pic_read_fields", "pic_read_particles", "pic_get_info",
             "pic_set_stream", "pic_sync", "pic_profile_enable", "pic_profile_read",
-            "pic_last_error", "pic_destroy"]
+            "pic_last_error", "pic_destroy",
+            "pic_batch_create", "pic_batch_add", "pic_batch_remove", "pic_batch_step",
+            "pic_batch_set_graph", "pic_batch_sync", "pic_batch_size", "pic_batch_last_error",
+            "pic_batch_destroy"]
 
 
 class PicError(RuntimeError):
@@ -93,6 +96,15 @@ def load_library(path: str = LIB_PATH):
         "pic_profile_read": ([P, C.POINTER(Profile)], C.c_int),
         "pic_last_error": ([P], C.c_char_p),
         "pic_destroy": ([P], None),
+        "pic_batch_create": ([I32, I32, C.POINTER(P)], C.c_int),
+        "pic_batch_add": ([P, P], C.c_int),
+        "pic_batch_remove": ([P, P], C.c_int),
+        "pic_batch_step": ([P, I32], C.c_int),
+        "pic_batch_set_graph": ([P, I32], C.c_int),
+        "pic_batch_sync": ([P], C.c_int),
+        "pic_batch_size": ([P, C.POINTER(I32)], C.c_int),
+        "pic_batch_last_error": ([P], C.c_char_p),
+        "pic_batch_destroy": ([P], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -247,6 +259,58 @@ class Context:
         p = Profile()
         self._check(self.lib.pic_profile_read(self.h, C.byref(p)))
         return {f: getattr(p, f) for f, _ in Profile._fields_}
+
+
+class Batch:
+    """One pic_batch: member Contexts stepped together.  Names follow the C ABI without the
+    ``pic_batch_`` prefix."""
+
+    def __init__(self, device=0, precision=0):
+        self.lib = load_library()
+        h = C.c_void_p()
+        st = self.lib.pic_batch_create(int(device), int(precision), C.byref(h))
+        if st != 0:
+            raise PicError(st, self.lib.pic_batch_last_error(None).decode())
+        self.h = h
+        self.members = []
+
+    def _check(self, st):
+        if st != 0:
+            raise PicError(st, self.lib.pic_batch_last_error(self.h).decode())
+
+    def add(self, ctx):
+        self._check(self.lib.pic_batch_add(self.h, ctx.h))
+        self.members.append(ctx)
+
+    def remove(self, ctx):
+        self._check(self.lib.pic_batch_remove(self.h, ctx.h))
+        self.members.remove(ctx)
+
+    def step(self, nsteps=1):
+        self._check(self.lib.pic_batch_step(self.h, int(nsteps)))
+
+    def set_graph(self, on=True):
+        self._check(self.lib.pic_batch_set_graph(self.h, 1 if on else 0))
+
+    def sync(self):
+        self._check(self.lib.pic_batch_sync(self.h))
+
+    def size(self):
+        n = C.c_int32()
+        self._check(self.lib.pic_batch_size(self.h, C.byref(n)))
+        return n.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pic_batch_destroy(self.h)
+            self.h = None
+            self.members = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def init_grid(grid, **kw) -> Context:

@@ -10,61 +10,17 @@
 #include <vector>
 
 #include "pic.h"
+#include "pic_ctx.h"
 #include "pic_internal.h"
+
+using pic::ProfEvents;
+using pic::SpeciesState;
 
 namespace {
 
 thread_local std::string g_init_error;
 
-struct SpeciesState {
-  bool loaded = false;
-  double q = 0, m = 1, w = 0;
-  int64_t cap = 0;         // slots allocated
-  int64_t n_loaded = 0;    // particles given at the last load
-  double *buf[2][5] = {};  // FP64 form: two copies of the state; perm maps sorted slot -> location
-  int32_t *mcell[2] = {};  // mixed form: cell key k * nx + i
-  float *mbuf[2][5] = {};  // mixed form: in-cell offsets f_x, f_z and u_x, u_y, u_z
-  int64_t *ids[2] = {};
-  int32_t *perm[2] = {};
-  int32_t *cs[2] = {};     // cell start offsets [ncells + 1]
-  uint32_t *locode = nullptr;
-  int32_t *cnt = nullptr;  // [9][ncells]
-  int32_t *arr = nullptr;  // [ncells] arrivals per cell, zero between cycles
-  int32_t *bsum = nullptr;
-};
-
-struct ProfEvents {
-  hipEvent_t ev[4];  // step start, after field solve, after particles, after sort
-};
-
 }  // namespace
-
-struct pic_ctx {
-  pic_grid_desc d{};
-  pic::GridArgs g{};
-  pic::LaserArgs laser{};
-  pic::TileArgs tiles{};
-  int S = 0;
-  hipStream_t stream = nullptr;
-  hipStream_t own_stream = nullptr;
-  double *E[2] = {}, *Ebar = nullptr, *H[2] = {}, *M = nullptr;
-  int ecur = 0, hcur = 0, cur = 0;
-  SpeciesState sp[PIC_MAX_SPECIES];
-  uint32_t *flags = nullptr;
-  uint8_t *tact[2] = {};   // active-tile flags of the current / next order
-  int32_t *tlist[2] = {};  // ordered active-tile lists, count at [ntiles]
-  int32_t tiles_alloc = 0, tiles_tx = 0, tiles_tz = 0;
-  int32_t *col_tile = nullptr, *row_tile = nullptr;  // cell column / row -> tile index
-  int64_t step = 0;
-  int64_t bytes = 0;
-  int32_t n_scan_blocks = 0;
-  std::string err;
-  // profiling
-  bool prof_on = false;
-  std::vector<ProfEvents> prof_ev;
-  size_t prof_used = 0;
-  pic_profile prof_acc{};
-};
 
 namespace {
 
@@ -156,6 +112,7 @@ pic::StepArgs step_args(pic_ctx *c, bool push) {
   a.g = c->g;
   a.t = c->tiles;
   a.mixed = mixed(c) ? 1 : 0;
+  a.n_scan_blocks = c->n_scan_blocks;
   a.nsp = c->S;
   const int cur = c->cur, nxt = 1 - c->cur;
   for (int s = 0; s < c->S; ++s) {
@@ -278,6 +235,37 @@ void prof_accumulate(pic_ctx *c) {
 }
 
 }  // namespace
+
+namespace pic {
+
+StepArgs cycle_step_args(pic_ctx *c, int p) {
+  const int saved = c->cur;
+  c->cur = p;
+  StepArgs a = step_args(c, true);
+  c->cur = saved;
+  a.Ebar = c->Ebar;
+  a.Hold = c->H[p];
+  a.Hnew = c->H[1 - p];
+  a.M = c->M;
+  return a;
+}
+
+FieldArgs cycle_field_args(pic_ctx *c, int p) {
+  FieldArgs fa{};
+  fa.g = c->g;
+  fa.laser = c->laser;
+  fa.t = (double)c->step * c->g.dt;
+  fa.M = c->M;
+  fa.E = c->E[p];
+  fa.H = c->H[p];
+  fa.E_new = c->E[1 - p];
+  fa.Ebar = c->Ebar;
+  fa.H_new = c->H[1 - p];
+  fa.M_clear = c->M;
+  return fa;
+}
+
+}  // namespace pic
 
 extern "C" {
 
@@ -512,6 +500,7 @@ pic_status pic_load_particles(pic_ctx *c, int32_t s, double q, double m, double 
       return fail(c, PIC_ERR_ARG, "tile too large: its LDS accumulators exceed 64 KiB");
   }
   HIP_TRY(c, hipMemsetAsync(c->flags, 0, sizeof(uint32_t), c->stream), "clear flags");
+  pic::batch_touch(c);
   return redeposit(c);
 }
 
@@ -528,6 +517,7 @@ pic_status pic_load_fields(pic_ctx *c, const double *e, const double *h) {
   if (e) HIP_TRY(c, hipMemcpy(c->E[c->ecur], e, 3 * nn * sizeof(double), hipMemcpyHostToDevice), "upload E");
   if (h) HIP_TRY(c, hipMemcpy(c->H[c->hcur], h, 3 * nc * sizeof(double), hipMemcpyHostToDevice), "upload H");
   HIP_TRY(c, hipMemsetAsync(c->flags, 0, sizeof(uint32_t), c->stream), "clear flags");
+  pic::batch_touch(c);
   return redeposit(c);
 }
 
@@ -535,12 +525,14 @@ pic_status pic_set_step(pic_ctx *c, int64_t step) {
   if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
   if (step < 0) return fail(c, PIC_ERR_ARG, "step must be >= 0");
   c->step = step;
+  pic::batch_touch(c);
   return PIC_OK;
 }
 
 pic_status pic_step(pic_ctx *c, int32_t nsteps) {
   if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
   if (nsteps < 0) return fail(c, PIC_ERR_ARG, "nsteps must be >= 0");
+  if (c->batch) return fail(c, PIC_ERR_STATE, "the context is stepped by a batch");
   bool any = false;
   for (int s = 0; s < c->S; ++s) any = any || c->sp[s].loaded;
   if (!any) return fail(c, PIC_ERR_STATE, "no particles loaded");
@@ -560,24 +552,10 @@ pic_status pic_step(pic_ctx *c, int32_t nsteps) {
       pe = &c->prof_ev[c->prof_used++];
       HIP_TRY(c, hipEventRecord(pe->ev[0], c->stream), "event record");
     }
-    pic::FieldArgs fa{};
-    fa.g = c->g;
-    fa.laser = c->laser;
-    fa.t = (double)c->step * c->g.dt;
-    fa.M = c->M;
-    fa.E = c->E[c->ecur];
-    fa.H = c->H[c->hcur];
-    fa.E_new = c->E[1 - c->ecur];
-    fa.Ebar = c->Ebar;
-    fa.H_new = c->H[1 - c->hcur];
-    fa.M_clear = c->M;
+    const pic::FieldArgs fa = pic::cycle_field_args(c, c->cur);
     HIP_TRY(c, pic::launch_field_solve(fa, c->stream), "field solve");
     if (pe) HIP_TRY(c, hipEventRecord(pe->ev[1], c->stream), "event record");
-    pic::StepArgs a = step_args(c, true);
-    a.Ebar = c->Ebar;
-    a.Hold = c->H[c->hcur];
-    a.Hnew = c->H[1 - c->hcur];
-    a.M = c->M;
+    const pic::StepArgs a = pic::cycle_step_args(c, c->cur);
     HIP_TRY(c, pic::launch_particles(a, true, c->stream), "particle kernel");
     if (pe) HIP_TRY(c, hipEventRecord(pe->ev[2], c->stream), "event record");
     HIP_TRY(c, pic::launch_sort(a, c->n_scan_blocks, c->stream), "sort kernels");
@@ -702,6 +680,7 @@ pic_status pic_get_info(pic_ctx *c, pic_info *info) {
 
 pic_status pic_set_stream(pic_ctx *c, void *stream) {
   if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
+  if (c->batch) return fail(c, PIC_ERR_STATE, "the context runs on its batch's stream");
   HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
   c->stream = stream ? static_cast<hipStream_t>(stream) : c->own_stream;
   return PIC_OK;
@@ -739,6 +718,7 @@ const char *pic_last_error(const pic_ctx *c) { return c ? c->err.c_str() : g_ini
 
 void pic_destroy(pic_ctx *c) {
   if (!c) return;
+  pic::batch_detach(c);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (int s = 0; s < PIC_MAX_SPECIES; ++s) free_species(c, c->sp[s]);
   const size_t nn = (size_t)c->g.nnodes, nc = (size_t)c->g.ncells;

@@ -64,6 +64,7 @@ struct StepArgs {
   GridArgs g;
   TileArgs t;
   int32_t mixed;             // 1: mixed-precision particle state and arithmetic
+  int32_t n_scan_blocks;     // blocks of the count scan per species
   int32_t nsp;               // species slots
   SpeciesArgs sp[kMaxSpecies];
   const double *Ebar;        // [3][nodes]
@@ -92,6 +93,35 @@ struct FieldArgs {
   double *M_clear;           // moment planes zeroed by the H update (NULL: keep)
 };
 
+// Many independent runs stepped together, each kernel launched once for all of them
+// (persistent blocks looping over work items).  Per run, the step and field arguments for both
+// buffer parities live in device memory, and the run's current parity and cycle count are
+// device counters, so one captured cycle can be replayed for any mix of runs.
+struct BatchArgs {
+  const StepArgs *step;      // [2 * nruns]: run r, parity p at 2 r + p
+  const FieldArgs *field;    // [2 * nruns]
+  int32_t *par;              // [nruns] buffer parity of the current cycle
+  int64_t *step_ctr;         // [nruns] cycles done (E^n is at step * dt)
+  int32_t nruns;
+  // exclusive prefix sums over runs ([nruns + 1]) of the work items of each kernel
+  const int32_t *pre_nodes;  // blocks of kBlock nodes
+  const int32_t *pre_cells;  // blocks of kBlock cells
+  const int32_t *pre_scan;   // scan blocks x species slots
+  const int32_t *pre_spec;   // species slots
+  const int32_t *pre_tflag;  // blocks of kBlock tiles
+  const int32_t *pre_one;    // one item per run
+  int32_t *pre_tiles;        // active tiles of the current order (written each cycle)
+  int32_t *pre_rank;         // active tiles x species slots (written each cycle)
+};
+
+struct BatchLaunch {
+  int32_t grid_small;        // persistent blocks of the element-wise and scan kernels
+  int32_t grid_particles;    // persistent blocks of the particle kernel
+  int32_t grid_rank;         // persistent blocks of the rank kernel
+  size_t lds_particles, lds_rank;
+  bool mixed;
+};
+
 size_t particle_lds_bytes(const GridArgs &g, const TileArgs &t, bool mixed);
 size_t rank_lds_bytes(const TileArgs &t);
 
@@ -99,6 +129,11 @@ hipError_t launch_field_solve(const FieldArgs &a, hipStream_t s);
 hipError_t launch_particles(const StepArgs &a, bool push, hipStream_t s);
 hipError_t launch_sort(const StepArgs &a, int32_t n_scan_blocks, hipStream_t s);
 hipError_t launch_iota(int32_t *p, int64_t n, hipStream_t s);
+// One cycle of every run of a batch (field solve, particles, sort, counters).
+hipError_t launch_batch_cycle(const BatchArgs &b, const BatchLaunch &l, hipStream_t s);
+// Persistent blocks per CU of the batched particle and rank kernels at the given LDS sizes.
+hipError_t batch_occupancy(bool mixed, size_t lds_particles, size_t lds_rank, int *per_cu_particles,
+                           int *per_cu_rank);
 // Build the active-tile flags and list of the order described by sp[].cs (into
 // tile_active_next / tile_list_next).
 hipError_t launch_tile_list(const StepArgs &a, bool from_next_order, hipStream_t s);

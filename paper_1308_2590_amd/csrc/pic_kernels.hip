@@ -148,9 +148,11 @@ __device__ void solve_node(const FieldArgs &a, int i, int k, double out[3]) {
   out[2] = (c02 * rhs[0] + c12 * rhs[1] + c22 * rhs[2]) / det;
 }
 
-__global__ __launch_bounds__(kBlock) void k_solve_e(const FieldArgs a) {
+// Kernel bodies take their block coordinates (and the time of E^n) as arguments: the
+// single-run kernels pass blockIdx, the batched persistent kernels the coordinates of a work
+// item within its run.
+__device__ __forceinline__ void solve_e_body(const FieldArgs &a, double tE, int64_t n) {
   const GridArgs &g = a.g;
-  int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= g.nnodes) return;
   int k = (int)(n / g.nxn), i = (int)(n - (int64_t)k * g.nxn);
   const int64_t nn = g.nnodes;
@@ -165,7 +167,7 @@ __global__ __launch_bounds__(kBlock) void k_solve_e(const FieldArgs a) {
       for (int r = 0; r < 3; ++r) ein[r] = a.E[r * nn + (int64_t)k * g.nxn + inner];
     }
     const double kappa = (g.dt - g.dx) / (g.dt + g.dx);
-    const double t0 = a.t, t1 = a.t + g.dt;
+    const double t0 = tE, t1 = tE + g.dt;
     const double z = (double)k * g.dz;
     int64_t nb = (int64_t)k * g.nxn + i, nin = (int64_t)k * g.nxn + inner;
 #pragma unroll
@@ -195,9 +197,12 @@ __global__ __launch_bounds__(kBlock) void k_solve_e(const FieldArgs a) {
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_update_h(const FieldArgs a) {
+__global__ __launch_bounds__(kBlock) void k_solve_e(const FieldArgs a) {
+  solve_e_body(a, a.t, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__device__ __forceinline__ void update_h_body(const FieldArgs &a, int64_t c) {
   const GridArgs &g = a.g;
-  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= g.ncells) return;
   const int nx = g.nx, nz = g.nz, nxn = g.nxn;
   int k = (int)(c / nx), i = (int)(c - (int64_t)k * nx);
@@ -220,6 +225,10 @@ __global__ __launch_bounds__(kBlock) void k_update_h(const FieldArgs a) {
     if (g.bc_x == PIC_BC_ABSORBING && i == nx - 1)
       for (int p = 0; p < g.n_planes; ++p) a.M_clear[p * nn + na + 1] = 0.0;
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_update_h(const FieldArgs a) {
+  update_h_body(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -476,13 +485,10 @@ struct Pstate<true> {
 // added into FP64 LDS accumulators and the FP64 moment planes.  The FP64 form needs about 240
 // VGPRs (two waves per SIMD); the FP32 form fits three.
 template <bool PUSH, bool MIXED>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2 + MIXED, 2 + MIXED)))
-void k_particles(const StepArgs a) {
+__device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
   using T = typename std::conditional<MIXED, float, double>::type;
   const GridArgs &g = a.g;
   const TileArgs &t = a.t;
-  const int tile = block_tile(t, a.tile_list);
-  if (tile < 0) return;
   const int tzi = tile / t.ntx, txi = tile - tzi * t.ntx;
   const int i0 = txi * t.tx, k0 = tzi * t.tz;
   const int i1 = min(i0 + t.tx, g.nx), k1 = min(k0 + t.tz, g.nz);
@@ -872,6 +878,14 @@ void k_particles(const StepArgs a) {
   }
 }
 
+template <bool PUSH, bool MIXED>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2 + MIXED, 2 + MIXED)))
+void k_particles(const StepArgs a) {
+  const int tile = block_tile(a.t, a.tile_list);
+  if (tile < 0) return;
+  particles_body<PUSH, MIXED>(a, tile);
+}
+
 // ------------------------------------------------------------------------------------------
 // Sort
 // ------------------------------------------------------------------------------------------
@@ -921,12 +935,12 @@ __device__ int block_excl_scan(int v, int *sh, int *total) {
   return off + inc - v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_counts(const StepArgs a) {
+__device__ __forceinline__ void scan_counts_body(const StepArgs &a, int bx, int s) {
   __shared__ int sh[kBlock / 64];
-  const SpeciesArgs &sp = a.sp[blockIdx.y];
+  const SpeciesArgs &sp = a.sp[s];
   if (!sp.active) return;
   const GridArgs &g = a.g;
-  const int64_t c0 = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
+  const int64_t c0 = (int64_t)bx * kScanBlock + (int64_t)threadIdx.x * kScanItems;
   int in[kScanItems];
   int sum = 0;
   // particles arriving in each cell (added by the particle kernel), cleared for the next cycle
@@ -949,12 +963,16 @@ __global__ __launch_bounds__(kBlock) void k_scan_counts(const StepArgs a) {
     if (c < g.ncells) sp.cs_new[c] = off;
     off += in[q];
   }
-  if (threadIdx.x == 0) sp.bsum[blockIdx.x] = total;
+  if (threadIdx.x == 0) sp.bsum[bx] = total;
 }
 
-__global__ __launch_bounds__(1024) void k_scan_blocks(const StepArgs a, int nblocks) {
+__global__ __launch_bounds__(kBlock) void k_scan_counts(const StepArgs a) {
+  scan_counts_body(a, blockIdx.x, blockIdx.y);
+}
+
+__device__ __forceinline__ void scan_blocks_body(const StepArgs &a, int s, int nblocks) {
   __shared__ int sh[1024 / 64];
-  const SpeciesArgs &sp = a.sp[blockIdx.x];
+  const SpeciesArgs &sp = a.sp[s];
   if (!sp.active) return;
   int carry = 0;
   for (int base = 0; base < nblocks; base += blockDim.x) {
@@ -968,15 +986,23 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const StepArgs a, int nblo
   if (threadIdx.x == 0) sp.cs_new[a.g.ncells] = carry;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_finish(const StepArgs a) {
-  const SpeciesArgs &sp = a.sp[blockIdx.y];
+__global__ __launch_bounds__(1024) void k_scan_blocks(const StepArgs a, int nblocks) {
+  scan_blocks_body(a, blockIdx.x, nblocks);
+}
+
+__device__ __forceinline__ void scan_finish_body(const StepArgs &a, int bx, int s) {
+  const SpeciesArgs &sp = a.sp[s];
   if (!sp.active) return;
-  const int add = sp.bsum[blockIdx.x];
-  const int64_t c0 = (int64_t)blockIdx.x * kScanBlock;
+  const int add = sp.bsum[bx];
+  const int64_t c0 = (int64_t)bx * kScanBlock;
   for (int q = threadIdx.x; q < kScanBlock; q += blockDim.x) {
     const int64_t c = c0 + q;
     if (c < a.g.ncells) sp.cs_new[c] += add;
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_finish(const StepArgs a) {
+  scan_finish_body(a, blockIdx.x, blockIdx.y);
 }
 
 // First slot, in the next order, of the particles moving from cell (ic, kc) with move code
@@ -1009,11 +1035,9 @@ __device__ int dest_base(const GridArgs &g, int ic, int kc, int d, Cnt cntv, Csn
 // slots in order, 64 at a time: particles with the same (cell, code) in a group of 64 get
 // consecutive ranks from per-code ballots, and a per-wave LDS counter carries the rank across
 // groups.
-__global__ __launch_bounds__(kBlock) void k_rank(const StepArgs a) {
+__device__ __forceinline__ void rank_body(const StepArgs &a, int tile, int species) {
   const GridArgs &g = a.g;
   const TileArgs &t = a.t;
-  const int tile = block_tile(t, a.tile_list);
-  if (tile < 0) return;
   const int tzi = tile / t.ntx, txi = tile - tzi * t.ntx;
   const int i0 = txi * t.tx, k0 = tzi * t.tz;
   const int i1 = min(i0 + t.tx, g.nx), k1 = min(k0 + t.tz, g.nz);
@@ -1032,7 +1056,7 @@ __global__ __launch_bounds__(kBlock) void k_rank(const StepArgs a) {
   // one block per (tile, species): twice the blocks of a per-tile launch, to overlap the
   // memory latency of the staging and walking phases
   {
-    const int s = blockIdx.y;
+    const int s = species;
     const SpeciesArgs &sp = a.sp[s];
     if (!sp.active) return;
     // counts of the tile and a one-cell ring (sources of the destinations reached from the
@@ -1148,12 +1172,17 @@ __global__ __launch_bounds__(kBlock) void k_rank(const StepArgs a) {
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_rank(const StepArgs a) {
+  const int tile = block_tile(a.t, a.tile_list);
+  if (tile < 0) return;
+  rank_body(a, tile, blockIdx.y);
+}
+
 // Flag per tile: does it hold particles of any species in the order given by the cell starts
 // (the current order, or the next one when from_next is set).  One thread per tile.
-__global__ __launch_bounds__(kBlock) void k_tile_flags(const StepArgs a, int from_next) {
+__device__ __forceinline__ void tile_flags_body(const StepArgs &a, int tile, int from_next) {
   const GridArgs &g = a.g;
   const TileArgs &t = a.t;
-  const int tile = blockIdx.x * blockDim.x + threadIdx.x;
   if (tile >= t.ntiles) return;
   const int tzi = tile / t.ntx, txi = tile - tzi * t.ntx;
   const int i0 = txi * t.tx, k0 = tzi * t.tz;
@@ -1168,11 +1197,15 @@ __global__ __launch_bounds__(kBlock) void k_tile_flags(const StepArgs a, int fro
   a.tile_active_next[tile] = (uint8_t)act;
 }
 
+__global__ __launch_bounds__(kBlock) void k_tile_flags(const StepArgs a, int from_next) {
+  tile_flags_body(a, blockIdx.x * blockDim.x + threadIdx.x, from_next);
+}
+
 // Ordered list of the flagged tiles, count at [ntiles].  One block; each thread takes a run of
 // kPer consecutive flags (loaded together), one block-wide scan per pass places the runs.  The
 // list order decides which block takes which tile: in tile order, the blocks of one XCD take
 // neighbouring tiles.
-__global__ __launch_bounds__(1024) void k_tile_compact(const StepArgs a) {
+__device__ __forceinline__ void tile_compact_body(const StepArgs &a) {
   __shared__ int sh[1024 / 64];
   constexpr int kPer = 16;
   const int ntiles = a.t.ntiles;
@@ -1194,6 +1227,168 @@ __global__ __launch_bounds__(1024) void k_tile_compact(const StepArgs a) {
     carry += total;
   }
   if (threadIdx.x == 0) a.tile_list_next[ntiles] = carry;
+}
+
+__global__ __launch_bounds__(1024) void k_tile_compact(const StepArgs a) { tile_compact_body(a); }
+
+// ------------------------------------------------------------------------------------------
+// Batched cycle: every kernel launched once for all runs of a batch.  Persistent blocks loop
+// over the work items of all runs (a run's items are numbered after the previous runs'); the
+// run of an item is found by binary search in the exclusive prefix of item counts.  Between
+// items a block synchronises, so LDS is reused safely.
+// ------------------------------------------------------------------------------------------
+
+// The run owning work item w: the largest r with pre[r] <= w (runs without items are skipped
+// because their prefix equals the next run's).
+__device__ __forceinline__ int find_run(const int32_t *pre, int nruns, int w) {
+  int lo = 0, hi = nruns - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= w) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// The argument tables are read through the constant address space: they do not change during
+// a launch, so their fields can be loaded into scalar registers like kernel arguments.
+__device__ __forceinline__ const StepArgs &run_step(const BatchArgs &b, int r) {
+  const int p = b.par[r];
+  const StepArgs __attribute__((address_space(4))) *t =
+      (const StepArgs __attribute__((address_space(4))) *)(b.step);
+  return *(const StepArgs *)(t + 2 * r + p);
+}
+__device__ __forceinline__ const FieldArgs &run_field(const BatchArgs &b, int r) {
+  const int p = b.par[r];
+  const FieldArgs __attribute__((address_space(4))) *t =
+      (const FieldArgs __attribute__((address_space(4))) *)(b.field);
+  return *(const FieldArgs *)(t + 2 * r + p);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_solve_e(const BatchArgs b) {
+  const int total = b.pre_nodes[b.nruns];
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int r = find_run(b.pre_nodes, b.nruns, w);
+    const FieldArgs &fa = run_field(b, r);
+    const double tE = (double)b.step_ctr[r] * fa.g.dt;
+    solve_e_body(fa, tE, (int64_t)(w - b.pre_nodes[r]) * kBlock + threadIdx.x);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void kb_update_h(const BatchArgs b) {
+  const int total = b.pre_cells[b.nruns];
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int r = find_run(b.pre_cells, b.nruns, w);
+    update_h_body(run_field(b, r), (int64_t)(w - b.pre_cells[r]) * kBlock + threadIdx.x);
+  }
+}
+
+// Work prefixes of the active tiles of every run's current order (one block).
+__global__ __launch_bounds__(1024) void kb_prefix(const BatchArgs b) {
+  __shared__ int sh[1024 / 64];
+  int carry_t = 0, carry_r = 0;
+  for (int base = 0; base < b.nruns; base += blockDim.x) {
+    const int r = base + threadIdx.x;
+    int nt = 0, nr = 0;
+    if (r < b.nruns) {
+      const StepArgs &sa = run_step(b, r);
+      nt = sa.tile_list[sa.t.ntiles];
+      nr = nt * sa.nsp;
+    }
+    int tot_t, tot_r;
+    const int off_t = block_excl_scan(nt, sh, &tot_t);
+    const int off_r = block_excl_scan(nr, sh, &tot_r);
+    if (r < b.nruns) {
+      b.pre_tiles[r] = carry_t + off_t;
+      b.pre_rank[r] = carry_r + off_r;
+    }
+    carry_t += tot_t;
+    carry_r += tot_r;
+  }
+  if (threadIdx.x == 0) {
+    b.pre_tiles[b.nruns] = carry_t;
+    b.pre_rank[b.nruns] = carry_r;
+  }
+}
+
+template <bool MIXED>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2 + MIXED, 2 + MIXED)))
+void kb_particles(const BatchArgs b) {
+  const int total = b.pre_tiles[b.nruns];
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int r = find_run(b.pre_tiles, b.nruns, w);
+    const StepArgs &sa = run_step(b, r);
+    particles_body<true, MIXED>(sa, sa.tile_list[w - b.pre_tiles[r]]);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void kb_scan_counts(const BatchArgs b) {
+  const int total = b.pre_scan[b.nruns];
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int r = find_run(b.pre_scan, b.nruns, w);
+    const StepArgs &sa = run_step(b, r);
+    const int li = w - b.pre_scan[r];
+    const int s = li / sa.n_scan_blocks;
+    scan_counts_body(sa, li - s * sa.n_scan_blocks, s);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(1024) void kb_scan_blocks(const BatchArgs b) {
+  const int total = b.pre_spec[b.nruns];
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int r = find_run(b.pre_spec, b.nruns, w);
+    const StepArgs &sa = run_step(b, r);
+    scan_blocks_body(sa, w - b.pre_spec[r], sa.n_scan_blocks);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void kb_scan_finish(const BatchArgs b) {
+  const int total = b.pre_scan[b.nruns];
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int r = find_run(b.pre_scan, b.nruns, w);
+    const StepArgs &sa = run_step(b, r);
+    const int li = w - b.pre_scan[r];
+    const int s = li / sa.n_scan_blocks;
+    scan_finish_body(sa, li - s * sa.n_scan_blocks, s);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void kb_tile_flags(const BatchArgs b) {
+  const int total = b.pre_tflag[b.nruns];
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int r = find_run(b.pre_tflag, b.nruns, w);
+    tile_flags_body(run_step(b, r), (w - b.pre_tflag[r]) * kBlock + threadIdx.x, 1);
+  }
+}
+
+__global__ __launch_bounds__(1024) void kb_tile_compact(const BatchArgs b) {
+  for (int r = blockIdx.x; r < b.nruns; r += gridDim.x) {
+    tile_compact_body(run_step(b, r));
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void kb_rank(const BatchArgs b) {
+  const int total = b.pre_rank[b.nruns];
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int r = find_run(b.pre_rank, b.nruns, w);
+    const StepArgs &sa = run_step(b, r);
+    const int li = w - b.pre_rank[r];
+    const int idx = li / sa.nsp;
+    rank_body(sa, sa.tile_list[idx], li - idx * sa.nsp);
+    __syncthreads();
+  }
+}
+
+// End of a cycle: flip every run's buffer parity and count the cycle.
+__global__ void kb_end(const BatchArgs b) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < b.nruns) {
+    b.par[r] ^= 1;
+    b.step_ctr[r] += 1;
+  }
 }
 
 __global__ void k_iota(int32_t *p, int64_t n) {
@@ -1256,6 +1451,38 @@ hipError_t launch_tile_list(const StepArgs &a, bool from_next_order, hipStream_t
   hipLaunchKernelGGL(k_tile_flags, dim3(ntb), dim3(kBlock), 0, s, a, from_next_order ? 1 : 0);
   hipLaunchKernelGGL(k_tile_compact, dim3(1), dim3(1024), 0, s, a);
   return hipGetLastError();
+}
+
+hipError_t launch_batch_cycle(const BatchArgs &b, const BatchLaunch &l, hipStream_t s) {
+  const dim3 blk(kBlock), small((unsigned)l.grid_small);
+  hipLaunchKernelGGL(kb_solve_e, small, blk, 0, s, b);
+  hipLaunchKernelGGL(kb_update_h, small, blk, 0, s, b);
+  hipLaunchKernelGGL(kb_prefix, dim3(1), dim3(1024), 0, s, b);
+  if (l.mixed)
+    hipLaunchKernelGGL(kb_particles<true>, dim3((unsigned)l.grid_particles), blk, l.lds_particles, s, b);
+  else
+    hipLaunchKernelGGL(kb_particles<false>, dim3((unsigned)l.grid_particles), blk, l.lds_particles, s, b);
+  hipLaunchKernelGGL(kb_scan_counts, small, blk, 0, s, b);
+  hipLaunchKernelGGL(kb_scan_blocks, small, dim3(1024), 0, s, b);
+  hipLaunchKernelGGL(kb_scan_finish, small, blk, 0, s, b);
+  hipLaunchKernelGGL(kb_tile_flags, small, blk, 0, s, b);
+  hipLaunchKernelGGL(kb_tile_compact, small, dim3(1024), 0, s, b);
+  hipLaunchKernelGGL(kb_rank, dim3((unsigned)l.grid_rank), blk, l.lds_rank, s, b);
+  hipLaunchKernelGGL(kb_end, dim3((unsigned)((b.nruns + kBlock - 1) / kBlock)), blk, 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t batch_occupancy(bool mixed, size_t lds_particles, size_t lds_rank, int *per_cu_particles,
+                           int *per_cu_rank) {
+  hipError_t e;
+  if (mixed)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_particles, kb_particles<true>, kBlock,
+                                                     lds_particles);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_particles, kb_particles<false>, kBlock,
+                                                     lds_particles);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_rank, kb_rank, kBlock, lds_rank);
 }
 
 hipError_t launch_iota(int32_t *p, int64_t n, hipStream_t s) {

@@ -96,3 +96,22 @@ def test_laser_needs_absorbing_axis():
     h = C.c_void_p()
     assert lib.pic_init_grid(C.byref(d), C.byref(h)) == 1
     assert "absorbing" in lib.pic_last_error(None).decode()
+
+
+def test_batch_argument_errors_without_device():
+    """The batch calls reject bad arguments before touching a device."""
+    import ctypes as C
+    from paper_1308_2590_amd import binding
+    lib = binding.load_library()
+    h = C.c_void_p()
+    assert lib.pic_batch_create(0, 7, C.byref(h)) == 1      # precision
+    assert b"precision" in lib.pic_batch_last_error(None)
+    assert lib.pic_batch_create(0, 0, None) == 1            # out is NULL
+    assert lib.pic_batch_step(None, 1) == 1
+    assert lib.pic_batch_add(None, None) == 1
+    assert lib.pic_batch_remove(None, None) == 1
+    assert lib.pic_batch_sync(None) == 1
+    n = C.c_int32(-1)
+    assert lib.pic_batch_size(None, C.byref(n)) == 1
+    assert lib.pic_batch_set_graph(None, 1) == 1
+    lib.pic_batch_destroy(None)
