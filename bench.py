@@ -77,6 +77,9 @@ def parse():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--compare-steps", type=int, default=20,
                     help="timed cycles of each FP64 / mixed comparison run (0 skips them)")
+    ap.add_argument("--serve-runs", type=int, default=256,
+                    help="requests of the batched serving stream (0 skips it)")
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="request arrivals per second")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before the workload, run one elementwise kernel that reads and writes "
                          "this many MiB (the reference dispatch for scaling HBM byte counters)")
@@ -171,6 +174,24 @@ def comparison(binding, torch, wl, steps, warmup, tile):
     return r
 
 
+def serving(args):
+    """The batched serving stream: independent foil runs arriving Poisson at serve_rate per
+    second (grid sides log-uniform in [32, 512], slab 5-15 % of x, density 10-200 n_c,
+    8-64 particles per cell, a0 in [0.5, 10], 100-1000 cycles each), mixed precision, admitted
+    into one batch by slots and device-memory footprint and stepped together."""
+    from paper_1308_2590_amd import serve
+    reqs = picgen.serving_stream(args.serve_runs, rate_per_s=args.serve_rate)
+    srv = serve.Server(picgen.request_workload, precision=picgen.PREC_MIXED, max_slots=256,
+                       budget_bytes=64 << 30, graph=True)
+    st = srv.run(reqs, realtime=True)
+    srv.close()
+    out = st.summary()
+    out.update({"arrival_rate_per_s": args.serve_rate, "precision": "mixed", "graph": True,
+                "offered_particle_steps": float(sum(
+                    2 * r.slab_cells * r.nz * r.ppc * r.steps for r in reqs))})
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -235,6 +256,9 @@ def main():
                        args.warmup, args.tile),
         ]
         print("[bench] comparison done", file=sys.stderr, flush=True)
+    if args.serve_runs > 0:
+        out["serving"] = serving(args)
+        print("[bench] serving done", file=sys.stderr, flush=True)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -298,3 +298,61 @@ def fp32_representable(wl: Workload) -> Workload:
             setattr(c, k, getattr(c, k).astype(np.float32).astype(np.float64))
         out.append(c)
     return replace(wl, species=out, grid=replace(wl.grid, precision=PREC_MIXED))
+
+
+@dataclass
+class Request:
+    """One run of a serving stream: its arrival time, the cycles it asks for, and the
+    parameters its foil workload is drawn from."""
+    rid: int
+    arrival_s: float
+    steps: int
+    nx: int
+    nz: int
+    slab_cells: int
+    density: float
+    ppc: int
+    a0: float
+    seed: int
+
+
+def serving_stream(n=256, rate_per_s=20.0, seed=5, *, nx_range=(32, 512), nz_range=(32, 512),
+                   slab_frac=(0.05, 0.15), density_range=(10.0, 200.0), ppc_range=(8, 64),
+                   a0_range=(0.5, 10.0), steps_range=(100, 1000)):
+    """A stream of independent foil runs: Poisson arrivals (exponential gaps) at rate_per_s;
+    grid sides log-uniform in nx_range / nz_range; slab width a uniform fraction of nx;
+    density log-uniform; particles per cell and cycles uniform integers; a0 uniform."""
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + 100 * 5 + seed))
+    t = 0.0
+    out = []
+    for r in range(n):
+        t += float(rng.exponential(1.0 / rate_per_s))
+        nx = int(round(math.exp(rng.uniform(math.log(nx_range[0]), math.log(nx_range[1])))))
+        nz = int(round(math.exp(rng.uniform(math.log(nz_range[0]), math.log(nz_range[1])))))
+        slab = max(1, int(round(rng.uniform(*slab_frac) * nx)))
+        dens = float(math.exp(rng.uniform(math.log(density_range[0]), math.log(density_range[1]))))
+        ppc = int(rng.integers(ppc_range[0], ppc_range[1] + 1))
+        a0 = float(rng.uniform(*a0_range))
+        steps = int(rng.integers(steps_range[0], steps_range[1] + 1))
+        out.append(Request(rid=r, arrival_s=t, steps=steps, nx=nx, nz=nz, slab_cells=slab,
+                           density=dens, ppc=ppc, a0=a0, seed=r))
+    return out
+
+
+def request_workload(req: Request, precision=PREC_MIXED) -> Workload:
+    """The foil workload of one request: slab centred in x, laser sigma = nz / 8 cells."""
+    nx, nz = req.nx, req.nz
+    i_lo = nx // 2 - req.slab_cells // 2
+    i_hi = i_lo + req.slab_cells
+    ci, ck = _slab_cells(nx, nz, i_lo, i_hi)
+    base = SEED_BASE + 100 * 5 + 1000 * (req.seed + 1)
+    el = make_species(np.random.Generator(np.random.PCG64(base)), ci, ck, req.ppc,
+                      q=-1.0, m=1.0, density=req.density, temperature_kev=1.0)
+    io = make_species(np.random.Generator(np.random.PCG64(base + 1)), ci, ck, req.ppc,
+                      q=1.0, m=ION_MASS, density=req.density, temperature_kev=0.0)
+    g = Grid(nx=nx, nz=nz, dx=FOIL_DX, dz=FOIL_DX, dt=FOIL_DT, bc_x=BC_ABSORBING,
+             bc_z=BC_PERIODIC, laser_a0=req.a0, laser_omega=1.0,
+             laser_sigma_z=(nz / 8.0) * FOIL_DX, laser_z_center=0.5 * nz * FOIL_DX,
+             laser_fwhm_t=200 * FOIL_DT, laser_t_center=400 * FOIL_DT, precision=precision)
+    return Workload(name=f"req{req.rid}_{nx}x{nz}", grid=g, species=[el, io], steps=req.steps,
+                    note=f"slab {req.slab_cells} cells, n={req.density:.1f}, ppc={req.ppc}, a0={req.a0:.2f}")
