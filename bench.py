@@ -73,7 +73,10 @@ def parse():
                     help="foil | foil_cm | lowdensity | uniform64a | uniform64b")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget for the CPU oracle baseline (0 disables it)")
-    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--tile", type=int, default=0,
+                    help="square tile side; 0 = the library's automatic choice")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="1: time candidate tile shapes during warmup and keep the fastest")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--compare-steps", type=int, default=20,
                     help="timed cycles of each FP64 / mixed comparison run (0 skips them)")
@@ -109,14 +112,19 @@ def cpu_baseline(wl, budget_s):
                       f"{el:.1f} s"}
 
 
-def run_gpu(binding, torch, wl, precision, steps, warmup, tile):
-    """Load the workload, run warmup cycles, then time `steps` cycles (wall clock around the
-    whole batch, HIP events per kernel group).  Returns the measurements."""
+def run_gpu(binding, torch, wl, precision, steps, warmup, tile, autotune=False):
+    """Load the workload, run warmup cycles (and the tile autotuner, whose cycles come before
+    the timed ones), then time `steps` cycles (wall clock around the whole batch, HIP events
+    per kernel group).  Returns the measurements."""
     S = wl.grid.n_species
     prec = picgen.PREC_MIXED if precision == "mixed" else picgen.PREC_FP64
     ctx = binding.Context(wl.grid, track_ids=False, tile=(tile, tile), precision=prec)
     for s, sp in enumerate(wl.species):
         ctx.load_particles(s, sp.q, sp.m, sp.w, sp.xi_x, sp.xi_z, sp.ux, sp.uy, sp.uz)
+    tuned = None
+    if autotune:
+        from paper_1308_2590_amd import autotune as at
+        tuned = at.tune_tiles(ctx)
     ctx.step(warmup)
     ctx.sync()
     torch.cuda.synchronize()
@@ -144,6 +152,10 @@ def run_gpu(binding, torch, wl, precision, steps, warmup, tile):
     alg_bytes = BYTES_PER_PARTICLE[precision] * n_mean + bytes_per_node(S) * wl.grid.n_nodes
     achieved = alg_bytes / (part_ms * 1e-3) / 1e9
     return {
+        "autotune": None if tuned is None else {
+            "best": list(tuned["best"]),
+            "ms_per_cycle": {f"{k[0]}x{k[1]}": v for k, v in tuned["ms_per_cycle"].items()},
+            "cycles_used": tuned["cycles_used"]},
         "value": n_mean * steps / wall,
         "ms_per_step": 1e3 * wall / steps,
         "particles": int(n_alive0),
@@ -160,13 +172,14 @@ def run_gpu(binding, torch, wl, precision, steps, warmup, tile):
     }
 
 
-def comparison(binding, torch, wl, steps, warmup, tile):
+def comparison(binding, torch, wl, steps, warmup, tile, autotune):
     r = {}
     for prec in ("fp64", "mixed"):
-        m = run_gpu(binding, torch, wl, prec, steps, warmup, tile)
+        m = run_gpu(binding, torch, wl, prec, steps, warmup, tile, autotune)
         r[prec] = {"particle_steps_per_s": m["value"], "ms_per_step": m["ms_per_step"],
                    "particle_kernel_ms": m["part_ms"], "particle_kernel_GBps": m["achieved"],
-                   "particle_kernel_frac_hbm": m["achieved"] / HBM_PEAK_GBS}
+                   "particle_kernel_frac_hbm": m["achieved"] / HBM_PEAK_GBS,
+                   "tile": m["tile"]}
     r["speedup_mixed_over_fp64"] = r["mixed"]["particle_steps_per_s"] / r["fp64"]["particle_steps_per_s"]
     r["particle_kernel_speedup"] = r["fp64"]["particle_kernel_ms"] / r["mixed"]["particle_kernel_ms"]
     r["workload"] = wl.name
@@ -211,7 +224,8 @@ def main():
 
     wl = picgen.named(args.workload)
     S = wl.grid.n_species
-    m = run_gpu(binding, torch, wl, args.precision, args.steps, args.warmup, args.tile)
+    m = run_gpu(binding, torch, wl, args.precision, args.steps, args.warmup, args.tile,
+                autotune=bool(args.autotune) and args.tile == 0)
     print(f"[bench] {wl.name} {args.precision}: {m['value']:.4g} particle-steps/s, "
           f"{m['ms_per_step']:.4f} ms/step", file=sys.stderr, flush=True)
     out = {
@@ -248,12 +262,14 @@ def main():
             "avg_launch_ms": m["part_ms"],
         },
         "breakdown_ms_per_step": m["breakdown"],
+        "autotune": m["autotune"],
     }
     if args.compare_steps > 0:
         out["fp64_vs_mixed"] = [
-            comparison(binding, torch, wl, args.compare_steps, args.warmup, args.tile),
+            comparison(binding, torch, wl, args.compare_steps, args.warmup, args.tile,
+                       bool(args.autotune) and args.tile == 0),
             comparison(binding, torch, picgen.named("foil_dense"), args.compare_steps,
-                       args.warmup, args.tile),
+                       args.warmup, args.tile, bool(args.autotune) and args.tile == 0),
         ]
         print("[bench] comparison done", file=sys.stderr, flush=True)
     if args.serve_runs > 0:

@@ -19,7 +19,8 @@ PIC_OK = 0
 STATUS = {0: "PIC_OK", 1: "PIC_ERR_ARG", 2: "PIC_ERR_OOM", 3: "PIC_ERR_DEVICE",
           4: "PIC_ERR_STATE", 5: "PIC_ERR_RANGE", 6: "PIC_ERR_OVERFLOW"}
 MAX_SPECIES = 8
-EXPORTED = ["pic_init_grid", "pic_load_particles", "pic_load_fields", "pic_set_step", "pic_step",
+EXPORTED = ["pic_init_grid", "pic_load_particles", "pic_load_fields", "pic_set_tiles",
+            "pic_set_step", "pic_step",
             "pic_read_moments", "pic_read_fields", "pic_read_particles", "pic_get_info",
             "pic_set_stream", "pic_sync", "pic_profile_enable", "pic_profile_read",
             "pic_last_error", "pic_destroy",
@@ -84,6 +85,7 @@ def load_library(path: str = LIB_PATH):
         "pic_init_grid": ([C.POINTER(GridDesc), C.POINTER(P)], C.c_int),
         "pic_load_particles": ([P, I32, D, D, D, I64, P, P, P, P, P], C.c_int),
         "pic_load_fields": ([P, P, P], C.c_int),
+        "pic_set_tiles": ([P, I32, I32], C.c_int),
         "pic_set_step": ([P, I64], C.c_int),
         "pic_step": ([P, I32], C.c_int),
         "pic_read_moments": ([P, P, I64], C.c_int),
@@ -198,6 +200,9 @@ class Context:
         if h is not None and h.size != 3 * self.nx * self.nz:
             raise ValueError("H must have 3 * cells values")
         self._check(self.lib.pic_load_fields(self.h, _p(e), _p(h)))
+
+    def set_tiles(self, tile_x, tile_z):
+        self._check(self.lib.pic_set_tiles(self.h, int(tile_x), int(tile_z)))
 
     def set_step(self, step):
         self._check(self.lib.pic_set_step(self.h, int(step)))

@@ -214,6 +214,32 @@ pic_status redeposit(pic_ctx *c) {
   return PIC_OK;
 }
 
+// Tile shape from the descriptor's tile_x / tile_z, or from the particles per occupied cell of
+// all loaded species when those are 0.  Waits for the stream (reads the cell starts).
+pic_status retile(pic_ctx *c) {
+  const int64_t nc = c->g.ncells;
+  std::vector<uint8_t> occ((size_t)nc, 0);
+  std::vector<int32_t> csh((size_t)nc + 1);
+  int64_t total = 0;
+  int nloaded = 0;
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  for (int ss = 0; ss < c->S; ++ss) {
+    if (!c->sp[ss].loaded) continue;
+    ++nloaded;
+    HIP_TRY(c, hipMemcpy(csh.data(), c->sp[ss].cs[c->cur], ((size_t)nc + 1) * sizeof(int32_t),
+                         hipMemcpyDeviceToHost), "read cell starts");
+    for (int64_t cc = 0; cc < nc; ++cc)
+      if (csh[cc + 1] > csh[cc]) occ[cc] = 1;
+    total += csh[nc];
+  }
+  int64_t occupied = 0;
+  for (uint8_t o : occ) occupied += o;
+  choose_tiles(c, total, occupied, nloaded);
+  if (pic::particle_lds_bytes(c->g, c->tiles, mixed(c)) > 65536)
+    return fail(c, PIC_ERR_ARG, "tile too large: its LDS accumulators exceed 64 KiB");
+  return PIC_OK;
+}
+
 void prof_accumulate(pic_ctx *c) {
   for (size_t q = 0; q < c->prof_used; ++q) {
     ProfEvents &p = c->prof_ev[q];
@@ -473,31 +499,9 @@ pic_status pic_load_particles(pic_ctx *c, int32_t s, double q, double m, double 
           "upload cell starts");
   HIP_TRY(c, pic::launch_iota(st.perm[c->cur], n, c->stream), "identity permutation");
   st.loaded = true;
-  // tiles from all loaded species
   {
-    std::vector<uint8_t> occ((size_t)nc, 0);
-    int64_t total = 0;
-    for (int ss = 0; ss < c->S; ++ss) {
-      if (!c->sp[ss].loaded) continue;
-      std::vector<int32_t> csh((size_t)nc + 1);
-      if (ss == s) {
-        csh = start;
-      } else {
-        HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
-        HIP_TRY(c, hipMemcpy(csh.data(), c->sp[ss].cs[c->cur], ((size_t)nc + 1) * sizeof(int32_t),
-                             hipMemcpyDeviceToHost), "read cell starts");
-      }
-      for (int64_t cc = 0; cc < nc; ++cc)
-        if (csh[cc + 1] > csh[cc]) occ[cc] = 1;
-      total += csh[nc];
-    }
-    int64_t occupied = 0;
-    for (uint8_t o : occ) occupied += o;
-    int nloaded = 0;
-    for (int ss = 0; ss < c->S; ++ss) nloaded += c->sp[ss].loaded ? 1 : 0;
-    choose_tiles(c, total, occupied, nloaded);
-    if (pic::particle_lds_bytes(c->g, c->tiles, mixed(c)) > 65536)
-      return fail(c, PIC_ERR_ARG, "tile too large: its LDS accumulators exceed 64 KiB");
+    const pic_status rt = retile(c);
+    if (rt != PIC_OK) return rt;
   }
   HIP_TRY(c, hipMemsetAsync(c->flags, 0, sizeof(uint32_t), c->stream), "clear flags");
   pic::batch_touch(c);
@@ -519,6 +523,31 @@ pic_status pic_load_fields(pic_ctx *c, const double *e, const double *h) {
   HIP_TRY(c, hipMemsetAsync(c->flags, 0, sizeof(uint32_t), c->stream), "clear flags");
   pic::batch_touch(c);
   return redeposit(c);
+}
+
+pic_status pic_set_tiles(pic_ctx *c, int32_t tile_x, int32_t tile_z) {
+  if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
+  if (tile_x < 0 || tile_z < 0 || tile_x > 64 || tile_z > 64 || ((tile_x == 0) != (tile_z == 0)))
+    return fail(c, PIC_ERR_ARG, "tile_x, tile_z must both be 0 or both in 1..64");
+  bool any = false;
+  for (int s = 0; s < c->S; ++s) any = any || c->sp[s].loaded;
+  if (!any) return fail(c, PIC_ERR_STATE, "no particles loaded");
+  const int32_t ox = c->d.tile_x, oz = c->d.tile_z;
+  c->d.tile_x = tile_x;
+  c->d.tile_z = tile_z;
+  pic_status st = retile(c);
+  if (st != PIC_OK) {
+    const std::string msg = c->err;
+    c->d.tile_x = ox;
+    c->d.tile_z = oz;
+    (void)retile(c);
+    c->err = msg;
+    return st;
+  }
+  if ((st = alloc_tiles(c)) != PIC_OK) return st;
+  if ((st = build_tile_list(c)) != PIC_OK) return st;
+  pic::batch_touch(c);
+  return PIC_OK;
 }
 
 pic_status pic_set_step(pic_ctx *c, int64_t step) {

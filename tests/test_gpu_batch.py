@@ -203,7 +203,6 @@ def test_batch_reload_member(pic):
     b.step(2)
     a_solo.step(2)
     c_solo.step(2)
-    sp = wls[4].species[0]
     new = picgen.random_small(99, nx=wls[2].grid.nx, nz=wls[2].grid.nz, ppc=5, bc_x=1,
                               dx=0.5, dz=0.4, dt=0.3).species[0]
     for ctx in (c, c_solo):
@@ -213,7 +212,6 @@ def test_batch_reload_member(pic):
     c_solo.step(3)
     compare(a, a_solo, 2, TOL64)
     compare(c, c_solo, 2, TOL64)
-    del sp
     b.close()
     for ctx in (a, a_solo, c, c_solo):
         ctx.close()
@@ -247,3 +245,27 @@ def test_batch_rules(pic):
     b.close()
     ctx.close()
     mixed.close()
+
+
+def test_set_tiles_and_autotune(pic):
+    """Re-tiling mid-run changes nothing but the order of atomic additions; the autotuner
+    leaves a valid shape applied; a shape too large for LDS is refused and the old one kept."""
+    from paper_1308_2590_amd import autotune
+    wl = workloads()[4]
+    a, b = make(pic, wl, 0, 4), make(pic, wl, 0, 4)
+    a.step(2)
+    b.step(2)
+    b.set_tiles(8, 2)
+    assert b.get_info()["tile"] == (8, 2)
+    a.step(3)
+    b.step(3)
+    compare(b, a, 2, TOL64)
+    with pytest.raises(pic.PicError) as e:
+        b.set_tiles(64, 64)
+    assert e.value.status == 1 and b.get_info()["tile"] == (8, 2)
+    res = autotune.tune_tiles(b, cycles=2, warmup=1)
+    assert tuple(b.get_info()["tile"]) == tuple(res["best"])
+    a.step(res["cycles_used"])
+    compare(b, a, 2, TOL64)
+    a.close()
+    b.close()
