@@ -12,7 +12,8 @@ from __future__ import annotations
 
 from . import binding
 
-CANDIDATES = [(4, 4), (8, 4), (16, 4), (32, 4), (8, 2), (16, 2), (32, 2), (8, 8), (16, 8)]
+CANDIDATES = [(4, 4), (8, 4), (16, 4), (32, 4), (8, 2), (16, 2), (32, 2), (16, 1), (32, 1),
+              (8, 8), (16, 8)]
 
 
 def tune_tiles(ctx, candidates=CANDIDATES, cycles=4, warmup=1):

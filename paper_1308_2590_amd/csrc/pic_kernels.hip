@@ -473,9 +473,10 @@ struct Pstate<true> {
   }
 };
 
-// One block per tile of cells (tile rows are cell rows), one wavefront per tile row.  The
-// row's particles (a contiguous range of the cell-sorted order) are split into 64 contiguous
-// runs, one per lane; run lengths differ by at most one.  A lane accumulates the deposits of
+// One block per tile of cells (tile rows are cell rows), one wavefront per tile row (or per
+// part of a row when the tile has fewer rows than wavefronts).  The row's particles (a
+// contiguous range of the cell-sorted order) are split into 64 contiguous runs, one per lane;
+// run lengths differ by at most one.  A lane accumulates the deposits of
 // particles that stay in their cell in registers and adds them to the LDS tile when its run
 // enters the next cell, so LDS atomics are issued once per (lane, cell) instead of once per
 // particle; particles changing cell go through a per-wave queue.  The pushed state of the
@@ -561,9 +562,16 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
     const typename Pstate<MIXED>::Src src(sp);
     const int32_t *perm = sp.perm;
     const int dens = 12 + s;
-    for (int r = k0 + wave; r < k1; r += nwaves) {
+    // A tile with fewer rows than wavefronts splits each row's particles into wpr contiguous
+    // parts, one per wavefront, so short tiles keep every wavefront busy.
+    const int nrows = k1 - k0;
+    const int wpr = nrows < nwaves ? nwaves / nrows : 1;
+    const int part = wave % wpr;
+    for (int r = k0 + wave / wpr; r < k1; r += nwaves / wpr) {
       const int64_t rowc = (int64_t)r * g.nx;
-      const int jb = sp.cs[rowc + i0], je = sp.cs[rowc + i1];
+      const int rb = sp.cs[rowc + i0], re = sp.cs[rowc + i1];
+      const int jb = rb + (int)((int64_t)(re - rb) * part / wpr);
+      const int je = rb + (int)((int64_t)(re - rb) * (part + 1) / wpr);
       const int L = je - jb;
       if (L == 0) continue;
       const int q = L >> 6, rr = L & 63;

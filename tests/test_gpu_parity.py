@@ -272,7 +272,7 @@ def test_tile_size_invariance(pic):
     wl = picgen.random_small(5, nx=37, nz=29, ppc=6, bc_x=1, dx=0.5, dz=0.5, dt=0.4)
     _say("tile invariance")
     res = []
-    for tile in [(4, 4), (8, 8), (16, 8), (5, 3), (32, 4)]:
+    for tile in [(4, 4), (8, 8), (16, 8), (5, 3), (32, 4), (16, 2), (32, 1)]:
         ctx = pic.Context(wl.grid, track_ids=True, tile=tile)
         for s, sp in enumerate(wl.species):
             ctx.load_particles(s, sp.q, sp.m, sp.w, sp.xi_x, sp.xi_z, sp.ux, sp.uy, sp.uz)
