@@ -32,11 +32,19 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1308_2590_amd", "csrc", "pic_kernels.h
 PROFILES = os.path.join(ROOT, "profiles")
 
 
-def measured_traffic(workload, precision):
+def parse_tile(text):
+    if "x" in str(text):
+        tx, tz = str(text).split("x")
+        return int(tx), int(tz)
+    return int(text), int(text)
+
+
+def measured_traffic(workload, precision, tile):
     """HBM bytes per launch of the particle kernel from the committed counter summary of this
-    workload and precision, if it was taken on the current kernel source (else None)."""
+    workload, precision and tile shape, if it was taken on the current kernel source (else
+    None)."""
     import hashlib
-    path = os.path.join(PROFILES, f"k_particles_{workload}_{precision}_traffic.md")
+    path = os.path.join(PROFILES, f"k_particles_{workload}_{precision}_{tile[0]}x{tile[1]}_traffic.md")
     if not os.path.exists(path):
         return None
     sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
@@ -73,8 +81,8 @@ def parse():
                     help="foil | foil_cm | lowdensity | uniform64a | uniform64b")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget for the CPU oracle baseline (0 disables it)")
-    ap.add_argument("--tile", type=int, default=0,
-                    help="square tile side; 0 = the library's automatic choice")
+    ap.add_argument("--tile", default="0",
+                    help="tile shape 'TXxTZ' or square side 'N'; 0 = the library's automatic choice")
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: time candidate tile shapes during warmup and keep the fastest")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
@@ -118,7 +126,7 @@ def run_gpu(binding, torch, wl, precision, steps, warmup, tile, autotune=False):
     per kernel group).  Returns the measurements."""
     S = wl.grid.n_species
     prec = picgen.PREC_MIXED if precision == "mixed" else picgen.PREC_FP64
-    ctx = binding.Context(wl.grid, track_ids=False, tile=(tile, tile), precision=prec)
+    ctx = binding.Context(wl.grid, track_ids=False, tile=tile, precision=prec)
     for s, sp in enumerate(wl.species):
         ctx.load_particles(s, sp.q, sp.m, sp.w, sp.xi_x, sp.xi_z, sp.ux, sp.uy, sp.uz)
     tuned = None
@@ -224,8 +232,9 @@ def main():
 
     wl = picgen.named(args.workload)
     S = wl.grid.n_species
-    m = run_gpu(binding, torch, wl, args.precision, args.steps, args.warmup, args.tile,
-                autotune=bool(args.autotune) and args.tile == 0)
+    tile = parse_tile(args.tile)
+    auto = bool(args.autotune) and tile == (0, 0)
+    m = run_gpu(binding, torch, wl, args.precision, args.steps, args.warmup, tile, autotune=auto)
     print(f"[bench] {wl.name} {args.precision}: {m['value']:.4g} particle-steps/s, "
           f"{m['ms_per_step']:.4f} ms/step", file=sys.stderr, flush=True)
     out = {
@@ -257,7 +266,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": m["achieved"] / HBM_PEAK_GBS,
-            "traffic": measured_traffic(args.workload, args.precision),
+            "traffic": measured_traffic(args.workload, args.precision, m["tile"]),
             "alg_bytes_per_launch": m["alg_bytes"],
             "avg_launch_ms": m["part_ms"],
         },
@@ -266,10 +275,9 @@ def main():
     }
     if args.compare_steps > 0:
         out["fp64_vs_mixed"] = [
-            comparison(binding, torch, wl, args.compare_steps, args.warmup, args.tile,
-                       bool(args.autotune) and args.tile == 0),
+            comparison(binding, torch, wl, args.compare_steps, args.warmup, tile, auto),
             comparison(binding, torch, picgen.named("foil_dense"), args.compare_steps,
-                       args.warmup, args.tile, bool(args.autotune) and args.tile == 0),
+                       args.warmup, tile, auto),
         ]
         print("[bench] comparison done", file=sys.stderr, flush=True)
     if args.serve_runs > 0:
