@@ -88,6 +88,8 @@ def parse():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--compare-steps", type=int, default=20,
                     help="timed cycles of each FP64 / mixed comparison run (0 skips them)")
+    ap.add_argument("--drift-steps", type=int, default=500,
+                    help="cycles of the FP64 / mixed drift comparison on the dense foil (0 skips it)")
     ap.add_argument("--serve-runs", type=int, default=256,
                     help="requests of the batched serving stream (0 skips it)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="request arrivals per second")
@@ -195,6 +197,51 @@ def comparison(binding, torch, wl, steps, warmup, tile, autotune):
     return r
 
 
+def drift(binding, steps, name="foil_dense"):
+    """After `steps` cycles from the same loaded state: each moment plane and field of the mixed
+    run against the FP64 run (relative L2 and max-norm errors), beside two controls:
+    - two FP64 runs that differ only in tile shape (the run-to-run spread from the order of
+      floating-point atomic additions, amplified by the particle dynamics over many cycles);
+    - an FP64 run started from the inputs rounded to the mixed form (the amplification of the
+      rounding at load alone).  The mixed run is also compared with this one."""
+    import numpy as np
+    wl = picgen.named(name)
+    wl32 = picgen.fp32_representable(wl)
+    runs = {}
+    for key, prec, tile, w in (("fp64", 0, (32, 1), wl), ("fp64_other_tiles", 0, (16, 4), wl),
+                               ("fp64_rounded_inputs", 0, (32, 1), wl32), ("mixed", 1, (4, 4), wl)):
+        ctx = binding.Context(w.grid, precision=prec, tile=tile)
+        for s, sp in enumerate(w.species):
+            ctx.load_particles(s, sp.q, sp.m, sp.w, sp.xi_x, sp.xi_z, sp.ux, sp.uy, sp.uz)
+        ctx.step(steps)
+        M = ctx.read_moments()
+        E, H = ctx.read_fields()
+        runs[key] = (M, E, H)
+        ctx.close()
+    names = ["S_xx", "S_xy", "S_xz", "S_yx", "S_yy", "S_yz", "S_zx", "S_zy", "S_zz",
+             "dj_x", "dj_y", "dj_z"] + [f"n_{s}" for s in range(wl.grid.n_species)]
+
+    def errs(a, b):
+        out = {}
+        for p, nm in enumerate(names):
+            d = a[0][p] - b[0][p]
+            out[nm] = {"l2": float(np.linalg.norm(d) / max(np.linalg.norm(b[0][p]), 1e-300)),
+                       "max": float(np.max(np.abs(d)) / max(np.max(np.abs(b[0][p])), 1e-300))}
+        for f, (ia, nm) in enumerate(((1, "E"), (2, "H"))):
+            for r in range(3):
+                d = a[ia][r] - b[ia][r]
+                out[f"{nm}{'xyz'[r]}"] = {
+                    "l2": float(np.linalg.norm(d) / max(np.linalg.norm(b[ia][r]), 1e-300)),
+                    "max": float(np.max(np.abs(d)) / max(np.max(np.abs(b[ia][r])), 1e-300))}
+        return out
+
+    return {"workload": wl.name, "cycles": steps,
+            "mixed_vs_fp64": errs(runs["mixed"], runs["fp64"]),
+            "fp64_vs_fp64_other_tiles": errs(runs["fp64_other_tiles"], runs["fp64"]),
+            "fp64_rounded_inputs_vs_fp64": errs(runs["fp64_rounded_inputs"], runs["fp64"]),
+            "mixed_vs_fp64_rounded_inputs": errs(runs["mixed"], runs["fp64_rounded_inputs"])}
+
+
 def serving(args):
     """The batched serving stream: independent foil runs arriving Poisson at serve_rate per
     second (grid sides log-uniform in [32, 512], slab 5-15 % of x, density 10-200 n_c,
@@ -280,6 +327,9 @@ def main():
                        args.warmup, tile, auto),
         ]
         print("[bench] comparison done", file=sys.stderr, flush=True)
+    if args.drift_steps > 0:
+        out["precision_drift"] = drift(binding, args.drift_steps)
+        print("[bench] drift done", file=sys.stderr, flush=True)
     if args.serve_runs > 0:
         out["serving"] = serving(args)
         print("[bench] serving done", file=sys.stderr, flush=True)
