@@ -113,6 +113,7 @@ pic::StepArgs step_args(pic_ctx *c, bool push) {
   a.t = c->tiles;
   a.mixed = mixed(c) ? 1 : 0;
   a.n_scan_blocks = c->n_scan_blocks;
+  a.n_scan1_blocks = c->n_scan1_blocks;
   a.nsp = c->S;
   const int cur = c->cur, nxt = 1 - c->cur;
   for (int s = 0; s < c->S; ++s) {
@@ -150,6 +151,7 @@ pic::StepArgs step_args(pic_ctx *c, bool push) {
   a.tile_list = c->tlist[cur];
   a.tile_active_next = c->tact[nxt];
   a.tile_list_next = c->tlist[nxt];
+  a.mtile = c->mtile;
   a.col_tile = c->col_tile;
   a.row_tile = c->row_tile;
   return a;
@@ -167,12 +169,18 @@ pic_status alloc_tiles(pic_ctx *c) {
     c->tact[b] = nullptr;
     c->tlist[b] = nullptr;
   }
+  dfree(c, c->mtile, (size_t)std::max(c->tiles_alloc, 1));
+  c->mtile = nullptr;
   c->tiles_alloc = 0;
   pic_status st;
   for (int b = 0; b < 2; ++b) {
     if ((st = dalloc(c, &c->tact[b], (size_t)nt, "alloc tile flags")) != PIC_OK) return st;
     if ((st = dalloc(c, &c->tlist[b], (size_t)nt + 1, "alloc tile list")) != PIC_OK) return st;
   }
+  if ((st = dalloc(c, &c->mtile, (size_t)nt, "alloc deposit flags")) != PIC_OK) return st;
+  // Moments deposited under another tiling may sit anywhere: every node is read (and
+  // cleared) by the next field solve.
+  HIP_TRY(c, hipMemset(c->mtile, 1, (size_t)nt), "deposit flags");
   c->tiles_alloc = nt;
   if (!c->col_tile) {
     if ((st = dalloc(c, &c->col_tile, (size_t)c->g.nx, "alloc tile map")) != PIC_OK) return st;
@@ -287,7 +295,12 @@ FieldArgs cycle_field_args(pic_ctx *c, int p) {
   fa.E_new = c->E[1 - p];
   fa.Ebar = c->Ebar;
   fa.H_new = c->H[1 - p];
-  fa.M_clear = c->M;
+  fa.mtile = c->mtile;
+  fa.tx = c->tiles.tx;
+  fa.tz = c->tiles.tz;
+  fa.ntx = c->tiles.ntx;
+  fa.r2dx = 1.0 / (2.0 * c->g.dx);
+  fa.r2dz = 1.0 / (2.0 * c->g.dz);
   return fa;
 }
 
@@ -361,6 +374,7 @@ pic_status pic_init_grid(const pic_grid_desc *d, pic_ctx **out) {
   c->laser = pic::LaserArgs{d->laser_a0, d->laser_omega, d->laser_sigma_z, d->laser_z_center,
                             d->laser_fwhm_t, d->laser_t_center};
   c->n_scan_blocks = (int32_t)((g.ncells + pic::kScanBlock - 1) / pic::kScanBlock);
+  c->n_scan1_blocks = (int32_t)((g.ncells + pic::kScan1Block - 1) / pic::kScan1Block);
   choose_tiles(c, 0, 0, 1);
 
   pic_status st = PIC_OK;
@@ -587,7 +601,7 @@ pic_status pic_step(pic_ctx *c, int32_t nsteps) {
     const pic::StepArgs a = pic::cycle_step_args(c, c->cur);
     HIP_TRY(c, pic::launch_particles(a, true, c->stream), "particle kernel");
     if (pe) HIP_TRY(c, hipEventRecord(pe->ev[2], c->stream), "event record");
-    HIP_TRY(c, pic::launch_sort(a, c->n_scan_blocks, c->stream), "sort kernels");
+    HIP_TRY(c, pic::launch_sort(a, c->stream), "sort kernels");
     if (pe) HIP_TRY(c, hipEventRecord(pe->ev[3], c->stream), "event record");
     c->ecur ^= 1;
     c->hcur ^= 1;
@@ -762,6 +776,7 @@ void pic_destroy(pic_ctx *c) {
     dfree(c, c->tact[b], (size_t)std::max(c->tiles_alloc, 1));
     dfree(c, c->tlist[b], ((size_t)c->tiles_alloc + 1) * sizeof(int32_t));
   }
+  dfree(c, c->mtile, (size_t)std::max(c->tiles_alloc, 1));
   dfree(c, c->col_tile, (size_t)c->g.nx * sizeof(int32_t));
   dfree(c, c->row_tile, (size_t)c->g.nz * sizeof(int32_t));
   for (auto &p : c->prof_ev)

@@ -50,11 +50,13 @@ struct pic_ctx {
   uint32_t *flags = nullptr;
   uint8_t *tact[2] = {};   // active-tile flags of the current / next order
   int32_t *tlist[2] = {};  // ordered active-tile lists, count at [ntiles]
+  uint8_t *mtile = nullptr;  // deposit flags of the tiles (nodes whose moments can be nonzero)
   int32_t tiles_alloc = 0, tiles_tx = 0, tiles_tz = 0;
   int32_t *col_tile = nullptr, *row_tile = nullptr;  // cell column / row -> tile index
   int64_t step = 0;
   int64_t bytes = 0;
   int32_t n_scan_blocks = 0;
+  int32_t n_scan1_blocks = 0;  // blocks of the scan of a cycle's sort
   std::string err;
   // profiling
   bool prof_on = false;

@@ -15,6 +15,8 @@ constexpr uint8_t kAbsorbed = 9;   // move code of a particle that left an absor
 constexpr int kBlock = 256;        // threads per block of the tile kernels (4 wavefronts)
 constexpr int kScanItems = 4;      // cells per thread in the count scan
 constexpr int kScanBlock = kBlock * kScanItems;
+constexpr int kScan1Items = 4;      // cells per thread in the scan of a cycle's sort
+constexpr int kScan1Block = kBlock * kScan1Items;
 
 struct GridArgs {
   int32_t nx, nz, nxn, nzn;  // cells and nodes per axis
@@ -78,6 +80,8 @@ struct StepArgs {
   const int32_t *tile_list;
   uint8_t *tile_active_next;
   int32_t *tile_list_next;
+  uint8_t *mtile;            // deposit flags set for every tile the fold reaches (may be NULL)
+  int32_t n_scan1_blocks;   // blocks of kScan1Block cells in a cycle's sort scan
   const int32_t *col_tile;   // [nx]: tile column of each cell column
   const int32_t *row_tile;   // [nz]: tile row of each cell row
 };
@@ -86,11 +90,16 @@ struct FieldArgs {
   GridArgs g;
   LaserArgs laser;
   double t;                  // time of E^n
-  const double *M;
+  double *M;                 // moment planes: read, then zeroed, where deposits can be
   const double *E;           // E^n
   const double *H;           // H^{n+1/2}
   double *E_new, *Ebar, *H_new;
-  double *M_clear;           // moment planes zeroed by the H update (NULL: keep)
+  // Deposit flags of the particle tiles (tx x tz cells, ntx per row): a node's moments are
+  // read only where the flag of the tile holding the node is set; the H update clears the
+  // flags for the next deposit.  NULL: every node is read and cleared.
+  uint8_t *mtile;
+  int32_t tx, tz, ntx;
+  double r2dx, r2dz;         // 1 / (2 dx), 1 / (2 dz) of the centred differences
 };
 
 // Many independent runs stepped together, each kernel launched once for all of them
@@ -126,8 +135,10 @@ size_t particle_lds_bytes(const GridArgs &g, const TileArgs &t, bool mixed);
 size_t rank_lds_bytes(const TileArgs &t);
 
 hipError_t launch_field_solve(const FieldArgs &a, hipStream_t s);
+// launch_particles also clears the next order's tile flags, which the sort's scan sets again;
+// launch_sort is the sort of a cycle (two-pass scan with tile flags and list, then ranks).
 hipError_t launch_particles(const StepArgs &a, bool push, hipStream_t s);
-hipError_t launch_sort(const StepArgs &a, int32_t n_scan_blocks, hipStream_t s);
+hipError_t launch_sort(const StepArgs &a, hipStream_t s);
 hipError_t launch_iota(int32_t *p, int64_t n, hipStream_t s);
 // One cycle of every run of a batch (field solve, particles, sort, counters).
 hipError_t launch_batch_cycle(const BatchArgs &b, const BatchLaunch &l, hipStream_t s);

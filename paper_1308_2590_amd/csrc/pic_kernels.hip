@@ -3,10 +3,11 @@
 // Field solve (FP64, one thread per node / cell):
 //   k_solve_e   Eq. (4) per node: E_new = (I + S)^{-1}[(I - S)E + dt(curl H - dj)] with curl H
 //               from the 2x2 neighbouring cells (Sec. 3.3 Step 5); on an absorbing x axis the
-//               thread of a boundary node recomputes its inner neighbour and applies the
-//               first-order Mur condition to E - E_inc (Steps 3, 4, 6); writes E-bar.
+//               thread of the inner node next to a boundary node also applies the first-order
+//               Mur condition to E - E_inc there (Steps 3, 4, 6); writes E-bar.  Moments are
+//               read, then cleared for the next deposit, only in tiles the deposit reached.
 //   k_update_h  Eq. (5) at cell centres with curl E from the 4 corner nodes (Steps 8-9), and
-//               clears the moment planes for the next deposit.
+//               clears the deposit flags of the tiles.
 // Particles (one block per tile of cells, one wavefront per row of the tile):
 //   k_particles gather E-bar (bilinear from the 4 corner nodes) and B (the particle's cell),
 //               implicit push (Eq. (2a) solved for the time-centred momentum), position
@@ -16,10 +17,11 @@
 //               It also counts the particles leaving each cell per move code and arriving in
 //               each cell.  Instantiated for FP64 and for the mixed form (FP32 particles).
 // Sort (stable by cell, removed particles dropped):
-//   k_scan_counts / k_scan_blocks / k_scan_finish  exclusive scan of the arrival counts ->
-//               next cell start offsets;
-//   k_tile_flags / k_tile_compact  the tiles holding particles in the next order, as flags and
-//               as an ordered list;
+//   k_scan_counts / k_scan_apply  exclusive scan of the arrival counts -> next cell start
+//               offsets (per block, then the block totals added), the tiles holding particles
+//               in the next order as flags and, from one extra block, as an ordered list;
+//   k_tile_flags / k_tile_compact  the same flags and list from cell starts (after loads);
+//   kb_scan_* / kb_tile_*  three-pass scan and separate tile passes of batched runs;
 //   k_rank      stable destination of every particle: cell start + particles arriving from
 //               source cells with a smaller key + rank within (source cell, move code),
 //               written as the next cycle's slot -> location permutation.
@@ -103,8 +105,26 @@ __device__ double incident_ey(const LaserArgs &L, double t, double x, double z) 
   return L.a0 * sin(L.omega * tau) * exp(-0.5 * sz * sz) * exp(-2.0 * 0.6931471805599453 * st * st);
 }
 
-// Eq. (4) at the node (i, k), i an interior column.
-__device__ void solve_node(const FieldArgs &a, int i, int k, double out[3]) {
+// Whether the moment planes of node (i, k) can hold a deposit: the flag of the particle tile
+// holding the node (the extra x column of an absorbing axis goes with the last cell column).
+// Elsewhere the planes are zero.
+__device__ __forceinline__ bool node_deposited(const FieldArgs &a, int i, int k) {
+  if (!a.mtile) return true;
+  const int ci = min(i, a.g.nx - 1);
+  return a.mtile[(k / a.tz) * a.ntx + ci / a.tx] != 0;
+}
+
+// Zero every moment plane of node n once its values have been read, so the next deposit
+// starts from zero.  Each node is read and cleared by one thread.
+__device__ __forceinline__ void clear_node_moments(const FieldArgs &a, int64_t n) {
+  for (int p = 0; p < a.g.n_planes; ++p) a.M[p * a.g.nnodes + n] = 0.0;
+}
+
+// Eq. (4) at the node (i, k), i an interior column.  Reads S-hat and delta-j of the node where
+// a deposit can have reached it (zero elsewhere) and clears its moment planes; returns E^n of
+// the node in eo.  Every load is issued before the first store (the compiler cannot tell the
+// planes apart, so a load after a store would wait for it).
+__device__ void solve_node(const FieldArgs &a, int i, int k, double eo[3], double out[3]) {
   const GridArgs &g = a.g;
   const int nx = g.nx, nz = g.nz;
   const int64_t nn = g.nnodes, nc = g.ncells;
@@ -113,21 +133,33 @@ __device__ void solve_node(const FieldArgs &a, int i, int k, double out[3]) {
   int64_t cUR = (int64_t)kU * nx + iR, cUL = (int64_t)kU * nx + iL;
   int64_t cDR = (int64_t)kD * nx + iR, cDL = (int64_t)kD * nx + iL;
   const double *Hx = a.H, *Hy = a.H + nc, *Hz = a.H + 2 * nc;
-  double dHx_dz = ((Hx[cUR] + Hx[cUL]) - (Hx[cDR] + Hx[cDL])) / (2.0 * g.dz);
-  double dHy_dz = ((Hy[cUR] + Hy[cUL]) - (Hy[cDR] + Hy[cDL])) / (2.0 * g.dz);
-  double dHy_dx = ((Hy[cUR] + Hy[cDR]) - (Hy[cUL] + Hy[cDL])) / (2.0 * g.dx);
-  double dHz_dx = ((Hz[cUR] + Hz[cDR]) - (Hz[cUL] + Hz[cDL])) / (2.0 * g.dx);
+  double dHx_dz = ((Hx[cUR] + Hx[cUL]) - (Hx[cDR] + Hx[cDL])) * a.r2dz;
+  double dHy_dz = ((Hy[cUR] + Hy[cUL]) - (Hy[cDR] + Hy[cDL])) * a.r2dz;
+  double dHy_dx = ((Hy[cUR] + Hy[cDR]) - (Hy[cUL] + Hy[cDL])) * a.r2dx;
+  double dHz_dx = ((Hz[cUR] + Hz[cDR]) - (Hz[cUL] + Hz[cDL])) * a.r2dx;
   double curl[3] = {-dHy_dz, dHx_dz - dHz_dx, dHy_dx};
   int64_t n = (int64_t)k * g.nxn + i;
-  double S[9], e[3], rhs[3];
-#pragma unroll
-  for (int r = 0; r < 9; ++r) S[r] = a.M[r * nn + n];
+  double S[9], J[3], e[3], rhs[3];
 #pragma unroll
   for (int r = 0; r < 3; ++r) e[r] = a.E[r * nn + n];
+  const bool dep = node_deposited(a, i, k);
+  if (dep) {
+#pragma unroll
+    for (int r = 0; r < 9; ++r) S[r] = a.M[r * nn + n];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) J[r] = a.M[(9 + r) * nn + n];
+  } else {
+#pragma unroll
+    for (int r = 0; r < 9; ++r) S[r] = 0.0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) J[r] = 0.0;
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) eo[r] = e[r];
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
     double se = S[3 * r] * e[0] + S[3 * r + 1] * e[1] + S[3 * r + 2] * e[2];
-    rhs[r] = (e[r] - se) + g.dt * (curl[r] - a.M[(9 + r) * nn + n]);
+    rhs[r] = (e[r] - se) + g.dt * (curl[r] - J[r]);
   }
   double A[9];
 #pragma unroll
@@ -143,57 +175,74 @@ __device__ void solve_node(const FieldArgs &a, int i, int k, double out[3]) {
   double c20 = A[1] * A[5] - A[2] * A[4];
   double c21 = A[2] * A[3] - A[0] * A[5];
   double c22 = A[0] * A[4] - A[1] * A[3];
-  out[0] = (c00 * rhs[0] + c10 * rhs[1] + c20 * rhs[2]) / det;
-  out[1] = (c01 * rhs[0] + c11 * rhs[1] + c21 * rhs[2]) / det;
-  out[2] = (c02 * rhs[0] + c12 * rhs[1] + c22 * rhs[2]) / det;
+  const double rdet = 1.0 / det;
+  out[0] = (c00 * rhs[0] + c10 * rhs[1] + c20 * rhs[2]) * rdet;
+  out[1] = (c01 * rhs[0] + c11 * rhs[1] + c21 * rhs[2]) * rdet;
+  out[2] = (c02 * rhs[0] + c12 * rhs[1] + c22 * rhs[2]) * rdet;
+  if (dep) clear_node_moments(a, n);
 }
 
-// Kernel bodies take their block coordinates (and the time of E^n) as arguments: the
-// single-run kernels pass blockIdx, the batched persistent kernels the coordinates of a work
-// item within its run.
+// E^{n+1} and E-bar = (E^n + E^{n+1}) / 2 of node n.
+__device__ __forceinline__ void write_e(const FieldArgs &a, int64_t n, const double eo[3],
+                                        const double en[3]) {
+  const int64_t nn = a.g.nnodes;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    a.E_new[r * nn + n] = en[r];
+    a.Ebar[r * nn + n] = 0.5 * (eo[r] + en[r]);
+  }
+}
+
+// Mur boundary (Step 3) at the column i = 0 or i = nx of an absorbing axis, from E^n (eo_in)
+// and the new E (ein) of the inner column next to it; the x = 0 column takes the source of
+// Step 4 on E_y.
+__device__ void mur_node(const FieldArgs &a, double tE, int i, int k, const double eo_in[3],
+                         const double ein[3]) {
+  const GridArgs &g = a.g;
+  const int64_t nn = g.nnodes;
+  const double kappa = (g.dt - g.dx) / (g.dt + g.dx);
+  const double t0 = tE, t1 = tE + g.dt;
+  const double z = (double)k * g.dz;
+  const int64_t nb = (int64_t)k * g.nxn + i;
+  double en[3], eo[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) eo[r] = a.E[r * nn + nb];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const double Eo_b = eo[r], Eo_in = eo_in[r];
+    if (i == 0) {
+      double i10 = 0.0, i01 = 0.0, i11 = 0.0, i00 = 0.0;
+      if (r == 1) {
+        i10 = incident_ey(a.laser, t1, 0.0, z);
+        i01 = incident_ey(a.laser, t0, g.dx, z);
+        i11 = incident_ey(a.laser, t1, g.dx, z);
+        i00 = incident_ey(a.laser, t0, 0.0, z);
+      }
+      en[r] = i10 + (Eo_in - i01) + kappa * ((ein[r] - i11) - (Eo_b - i00));
+    } else {
+      en[r] = Eo_in + kappa * (ein[r] - Eo_b);
+    }
+  }
+  write_e(a, nb, eo, en);
+  // the boundary node takes deposits too; its planes are not used by the solve
+  if (node_deposited(a, i, k)) clear_node_moments(a, nb);
+}
+
+// One node of the E solve.  On an absorbing axis the thread of the inner column next to a
+// boundary column also writes that boundary column, so every node's moments are read and
+// cleared by a single thread (an absorbing axis has nx >= 2).
 __device__ __forceinline__ void solve_e_body(const FieldArgs &a, double tE, int64_t n) {
   const GridArgs &g = a.g;
   if (n >= g.nnodes) return;
-  int k = (int)(n / g.nxn), i = (int)(n - (int64_t)k * g.nxn);
-  const int64_t nn = g.nnodes;
-  double en[3];
-  if (g.bc_x == PIC_BC_ABSORBING && (i == 0 || i == g.nx)) {
-    // Mur boundary (Step 3), the x = 0 column taking the source of Step 4 on E_y.
-    const int inner = (i == 0) ? 1 : g.nx - 1;
-    double ein[3];
-    if (g.nx >= 2) {
-      solve_node(a, inner, k, ein);
-    } else {
-      for (int r = 0; r < 3; ++r) ein[r] = a.E[r * nn + (int64_t)k * g.nxn + inner];
-    }
-    const double kappa = (g.dt - g.dx) / (g.dt + g.dx);
-    const double t0 = tE, t1 = tE + g.dt;
-    const double z = (double)k * g.dz;
-    int64_t nb = (int64_t)k * g.nxn + i, nin = (int64_t)k * g.nxn + inner;
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      double Eo_b = a.E[r * nn + nb], Eo_in = a.E[r * nn + nin];
-      if (i == 0) {
-        double i10 = 0.0, i01 = 0.0, i11 = 0.0, i00 = 0.0;
-        if (r == 1) {
-          i10 = incident_ey(a.laser, t1, 0.0, z);
-          i01 = incident_ey(a.laser, t0, g.dx, z);
-          i11 = incident_ey(a.laser, t1, g.dx, z);
-          i00 = incident_ey(a.laser, t0, 0.0, z);
-        }
-        en[r] = i10 + (Eo_in - i01) + kappa * ((ein[r] - i11) - (Eo_b - i00));
-      } else {
-        en[r] = Eo_in + kappa * (ein[r] - Eo_b);
-      }
-    }
-  } else {
-    solve_node(a, i, k, en);
-  }
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    double eo = a.E[r * nn + n];
-    a.E_new[r * nn + n] = en[r];
-    a.Ebar[r * nn + n] = 0.5 * (eo + en[r]);
+  const int k = (int)(n / g.nxn), i = (int)(n - (int64_t)k * g.nxn);
+  const bool absorbing = g.bc_x == PIC_BC_ABSORBING;
+  if (absorbing && (i == 0 || i == g.nx)) return;
+  double eo[3], en[3];
+  solve_node(a, i, k, eo, en);
+  write_e(a, n, eo, en);
+  if (absorbing) {
+    if (i == 1) mur_node(a, tE, 0, k, eo, en);
+    if (i == g.nx - 1) mur_node(a, tE, g.nx, k, eo, en);
   }
 }
 
@@ -212,19 +261,17 @@ __device__ __forceinline__ void update_h_body(const FieldArgs &a, int64_t c) {
   int64_t na = (int64_t)k * nxn + i, nb = (int64_t)k * nxn + i1;
   int64_t ncn = (int64_t)k1 * nxn + i, nd = (int64_t)k1 * nxn + i1;
   const double *Ex = a.E_new, *Ey = a.E_new + nn, *Ez = a.E_new + 2 * nn;
-  double dEx_dz = ((Ex[ncn] + Ex[nd]) - (Ex[na] + Ex[nb])) / (2.0 * g.dz);
-  double dEy_dz = ((Ey[ncn] + Ey[nd]) - (Ey[na] + Ey[nb])) / (2.0 * g.dz);
-  double dEy_dx = ((Ey[nb] + Ey[nd]) - (Ey[na] + Ey[ncn])) / (2.0 * g.dx);
-  double dEz_dx = ((Ez[nb] + Ez[nd]) - (Ez[na] + Ez[ncn])) / (2.0 * g.dx);
-  a.H_new[c] = a.H[c] - g.dt * (-dEy_dz);
-  a.H_new[nc + c] = a.H[nc + c] - g.dt * (dEx_dz - dEz_dx);
-  a.H_new[2 * nc + c] = a.H[2 * nc + c] - g.dt * dEy_dx;
-  if (a.M_clear) {
-    // Node (i, k) belongs to cell (i, k); the extra x column of an absorbing axis to i = nx-1.
-    for (int p = 0; p < g.n_planes; ++p) a.M_clear[p * nn + na] = 0.0;
-    if (g.bc_x == PIC_BC_ABSORBING && i == nx - 1)
-      for (int p = 0; p < g.n_planes; ++p) a.M_clear[p * nn + na + 1] = 0.0;
-  }
+  double dEx_dz = ((Ex[ncn] + Ex[nd]) - (Ex[na] + Ex[nb])) * a.r2dz;
+  double dEy_dz = ((Ey[ncn] + Ey[nd]) - (Ey[na] + Ey[nb])) * a.r2dz;
+  double dEy_dx = ((Ey[nb] + Ey[nd]) - (Ey[na] + Ey[ncn])) * a.r2dx;
+  double dEz_dx = ((Ez[nb] + Ez[nd]) - (Ez[na] + Ez[ncn])) * a.r2dx;
+  const double h0 = a.H[c], h1 = a.H[nc + c], h2 = a.H[2 * nc + c];  // loaded before any store
+  a.H_new[c] = h0 - g.dt * (-dEy_dz);
+  a.H_new[nc + c] = h1 - g.dt * (dEx_dz - dEz_dx);
+  a.H_new[2 * nc + c] = h2 - g.dt * dEy_dx;
+  // The E solve has read the deposit flags: clear them for the next deposit (one thread per
+  // tile, the one of its first cell).
+  if (a.mtile && i % a.tx == 0 && k % a.tz == 0) a.mtile[(k / a.tz) * a.ntx + i / a.tx] = 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_update_h(const FieldArgs a) {
@@ -869,6 +916,18 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
     }
   }
   __syncthreads();
+  // Flag every tile that holds a node the fold can reach (nodes i0-1 .. i0+tx+1 by
+  // k0-1 .. k0+tz+1): the field solve reads and clears the moment planes only there.  Six
+  // sample columns and rows cover every tile they cross, tx or tz of 1 included.
+  if (a.mtile && threadIdx.x < 36) {
+    const int sx = threadIdx.x % 6, sz = threadIdx.x / 6;
+    int gx = i0 + (sx < 3 ? sx - 1 : t.tx + sx - 4);
+    int gz = k0 + (sz < 3 ? sz - 1 : t.tz + sz - 4);
+    bool in = true;
+    if (g.bc_x == PIC_BC_PERIODIC) gx = wrap_any(gx, g.nx); else in = gx >= 0 && gx <= g.nx;
+    gz = wrap_any(gz, g.nz);
+    if (in) a.mtile[(gz / t.tz) * t.ntx + min(gx, g.nx - 1) / t.tx] = 1;
+  }
   // fold the tile's accumulators into the global FP64 moment planes
   for (int e = threadIdx.x; e < g.n_planes * plane; e += blockDim.x) {
     const double v = acc[e];
@@ -889,6 +948,9 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
 template <bool PUSH, bool MIXED>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2 + MIXED, 2 + MIXED)))
 void k_particles(const StepArgs a) {
+  // clear the next order's tile flags (set by the scan of this cycle's sort); the grid has a
+  // block for every tile index
+  if (threadIdx.x == 0 && (int)blockIdx.x < a.t.ntiles) a.tile_active_next[blockIdx.x] = 0;
   const int tile = block_tile(a.t, a.tile_list);
   if (tile < 0) return;
   particles_body<PUSH, MIXED>(a, tile);
@@ -974,10 +1036,6 @@ __device__ __forceinline__ void scan_counts_body(const StepArgs &a, int bx, int 
   if (threadIdx.x == 0) sp.bsum[bx] = total;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_counts(const StepArgs a) {
-  scan_counts_body(a, blockIdx.x, blockIdx.y);
-}
-
 __device__ __forceinline__ void scan_blocks_body(const StepArgs &a, int s, int nblocks) {
   __shared__ int sh[1024 / 64];
   const SpeciesArgs &sp = a.sp[s];
@@ -994,10 +1052,6 @@ __device__ __forceinline__ void scan_blocks_body(const StepArgs &a, int s, int n
   if (threadIdx.x == 0) sp.cs_new[a.g.ncells] = carry;
 }
 
-__global__ __launch_bounds__(1024) void k_scan_blocks(const StepArgs a, int nblocks) {
-  scan_blocks_body(a, blockIdx.x, nblocks);
-}
-
 __device__ __forceinline__ void scan_finish_body(const StepArgs &a, int bx, int s) {
   const SpeciesArgs &sp = a.sp[s];
   if (!sp.active) return;
@@ -1007,10 +1061,6 @@ __device__ __forceinline__ void scan_finish_body(const StepArgs &a, int bx, int 
     const int64_t c = c0 + q;
     if (c < a.g.ncells) sp.cs_new[c] += add;
   }
-}
-
-__global__ __launch_bounds__(kBlock) void k_scan_finish(const StepArgs a) {
-  scan_finish_body(a, blockIdx.x, blockIdx.y);
 }
 
 // First slot, in the next order, of the particles moving from cell (ic, kc) with move code
@@ -1109,13 +1159,41 @@ __device__ __forceinline__ void rank_body(const StepArgs &a, int tile, int speci
     }
     __syncthreads();
     const int total = sp.cs_new[g.ncells];
-    for (int r = k0 + wave; r < k1; r += nwaves) {
+    // A tile with fewer rows than wavefronts splits each row's slots into wpr contiguous
+    // parts, one per wavefront.  A part that starts inside a cell first counts, per move code,
+    // that cell's slots before the part, so its ranks continue the ones of the parts before.
+    const int nrows = k1 - k0;
+    const int wpr = nrows < nwaves ? nwaves / nrows : 1;
+    const int part = wave % wpr;
+    for (int r = k0 + wave / wpr; r < k1; r += nwaves / wpr) {
       const int64_t rowc = (int64_t)r * g.nx;
       const int lk = r - k0;
       for (int q = lane; q <= cw; q += 64) rowcs[q] = sp.cs[rowc + i0 + q];
       for (int q = lane; q < cw * 10; q += 64) ctr[q] = 0;
       wave_sync();
-      const int jb = rowcs[0], je = rowcs[cw];
+      const int rb = rowcs[0], re = rowcs[cw];
+      const int jb = rb + (int)((int64_t)(re - rb) * part / wpr);
+      const int je = rb + (int)((int64_t)(re - rb) * (part + 1) / wpr);
+      if (part > 0 && jb < je) {
+        int lo = 0, hi = cw - 1;  // the cell holding slot jb
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (rowcs[mid] <= jb) lo = mid; else hi = mid - 1;
+        }
+        int before[kMoveCodes] = {};
+        for (int b0 = rowcs[lo]; b0 < jb; b0 += 64) {
+          const int j = b0 + lane;
+          const int d = j < jb ? (int)(sp.locode[j] & 15u) : kAbsorbed;
+#pragma unroll
+          for (int dd = 0; dd < kMoveCodes; ++dd) before[dd] += __popcll(__ballot(d == dd));
+        }
+        if (lane < kMoveCodes) {
+#pragma unroll
+          for (int dd = 0; dd < kMoveCodes; ++dd)
+            if (lane == dd) ctr[lo * 10 + dd] = before[dd];
+        }
+        wave_sync();
+      }
       // the row's move codes are loaded kGroups groups of 64 at a time (indices clamped into
       // the row), then ranked group by group
       constexpr int kGroups = 8;
@@ -1222,11 +1300,17 @@ __device__ __forceinline__ void tile_compact_body(const StepArgs &a) {
     const int tb = pbase + (int)threadIdx.x * kPer;
     uint8_t f[kPer];
     int n = 0;
+    if (tb + kPer <= ntiles) {  // 16 flags in one load (tb is a multiple of 16)
+      const uint4 v = *reinterpret_cast<const uint4 *>(a.tile_active_next + tb);
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      f[q] = (tb + q < ntiles) ? a.tile_active_next[tb + q] : (uint8_t)0;
-      n += f[q];
+      for (int q = 0; q < kPer; ++q) f[q] = (uint8_t)(w[q >> 2] >> (8 * (q & 3)));
+    } else {
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) f[q] = (tb + q < ntiles) ? a.tile_active_next[tb + q] : (uint8_t)0;
     }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) n += f[q];
     int total;
     int pos = carry + block_excl_scan(n, sh, &total);
 #pragma unroll
@@ -1238,6 +1322,119 @@ __device__ __forceinline__ void tile_compact_body(const StepArgs &a) {
 }
 
 __global__ __launch_bounds__(1024) void k_tile_compact(const StepArgs a) { tile_compact_body(a); }
+
+// ---- two-pass scan of a cycle's sort --------------------------------------------------------
+// Pass 1 (k_scan_counts): per block of kScan1Block cells, the exclusive scan of the arrival
+// counts within the block (cleared for the next cycle), the block total, and the next order's
+// tile flags (a tile is active when particles arrive in one of its cells; the particle kernel
+// of the cycle cleared the flags).  Pass 2 (k_scan_apply): every block adds the totals of the
+// blocks before it; one extra block compacts the tile flags into the ordered tile list.
+__global__ __launch_bounds__(kBlock) void k_scan_counts(const StepArgs a) {
+  __shared__ int sh[kBlock / 64];
+  const int s = blockIdx.y, bx = blockIdx.x;
+  const SpeciesArgs &sp = a.sp[s];
+  if (!sp.active) return;
+  const GridArgs &g = a.g;
+  const int64_t c0 = (int64_t)bx * kScan1Block + (int64_t)threadIdx.x * kScan1Items;
+  int in[kScan1Items];
+  if (c0 + kScan1Items <= g.ncells) {
+    int4 *p4 = reinterpret_cast<int4 *>(sp.arr + c0);
+#pragma unroll
+    for (int q = 0; q < kScan1Items / 4; ++q) {
+      const int4 v = p4[q];
+      in[4 * q] = v.x;
+      in[4 * q + 1] = v.y;
+      in[4 * q + 2] = v.z;
+      in[4 * q + 3] = v.w;
+      if (v.x | v.y | v.z | v.w) p4[q] = make_int4(0, 0, 0, 0);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < kScan1Items; ++q) {
+      const int64_t c = c0 + q;
+      int v = 0;
+      if (c < g.ncells) {
+        v = sp.arr[c];
+        if (v) sp.arr[c] = 0;
+      }
+      in[q] = v;
+    }
+  }
+  int sum = 0;
+#pragma unroll
+  for (int q = 0; q < kScan1Items; ++q) sum += in[q];
+  if (sum) {
+    int k = (int)(c0 / g.nx), i = (int)(c0 - (int64_t)k * g.nx);
+#pragma unroll
+    for (int q = 0; q < kScan1Items; ++q) {
+      if (in[q] && k < g.nz) a.tile_active_next[a.row_tile[k] * a.t.ntx + a.col_tile[i]] = 1;
+      if (++i == g.nx) {
+        i = 0;
+        ++k;
+      }
+    }
+  }
+  int total;
+  int run = block_excl_scan(sum, sh, &total);
+  if (c0 + kScan1Items <= g.ncells) {
+    int4 *o4 = reinterpret_cast<int4 *>(sp.cs_new + c0);
+#pragma unroll
+    for (int q = 0; q < kScan1Items / 4; ++q) {
+      int4 v;
+      v.x = run;
+      run += in[4 * q];
+      v.y = run;
+      run += in[4 * q + 1];
+      v.z = run;
+      run += in[4 * q + 2];
+      v.w = run;
+      run += in[4 * q + 3];
+      o4[q] = v;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < kScan1Items; ++q) {
+      const int64_t c = c0 + q;
+      if (c < g.ncells) sp.cs_new[c] = run;
+      run += in[q];
+    }
+  }
+  if (threadIdx.x == 0) sp.bsum[bx] = total;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_apply(const StepArgs a) {
+  __shared__ int sh[kBlock / 64];
+  const int s = blockIdx.y, bx = blockIdx.x;
+  const int nb = a.n_scan1_blocks;
+  if (bx == nb) {
+    if (s == 0) tile_compact_body(a);
+    return;
+  }
+  const SpeciesArgs &sp = a.sp[s];
+  if (!sp.active) return;
+  int part = 0;
+  for (int b = threadIdx.x; b < bx; b += blockDim.x) part += sp.bsum[b];
+  int prefix;
+  (void)block_excl_scan(part, sh, &prefix);
+  const GridArgs &g = a.g;
+  const int64_t c0 = (int64_t)bx * kScan1Block + (int64_t)threadIdx.x * kScan1Items;
+  if (c0 + kScan1Items <= g.ncells) {
+    int4 *o4 = reinterpret_cast<int4 *>(sp.cs_new + c0);
+#pragma unroll
+    for (int q = 0; q < kScan1Items / 4; ++q) {
+      int4 v = o4[q];
+      v.x += prefix;
+      v.y += prefix;
+      v.z += prefix;
+      v.w += prefix;
+      o4[q] = v;
+    }
+  } else {
+    for (int q = 0; q < kScan1Items; ++q)
+      if (c0 + q < g.ncells) sp.cs_new[c0 + q] += prefix;
+  }
+  if (bx == nb - 1 && threadIdx.x == 0) sp.cs_new[g.ncells] = prefix + sp.bsum[bx];
+}
 
 // ------------------------------------------------------------------------------------------
 // Batched cycle: every kernel launched once for all runs of a batch.  Persistent blocks loop
@@ -1442,13 +1639,11 @@ hipError_t launch_particles(const StepArgs &a, bool push, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_sort(const StepArgs &a, int32_t n_scan_blocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan_counts, dim3((unsigned)n_scan_blocks, (unsigned)a.nsp), dim3(kBlock), 0, s, a);
-  hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)a.nsp), dim3(1024), 0, s, a, n_scan_blocks);
-  hipLaunchKernelGGL(k_scan_finish, dim3((unsigned)n_scan_blocks, (unsigned)a.nsp), dim3(kBlock), 0, s, a);
-  const unsigned ntb = (unsigned)((a.t.ntiles + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_tile_flags, dim3(ntb), dim3(kBlock), 0, s, a, 1);
-  hipLaunchKernelGGL(k_tile_compact, dim3(1), dim3(1024), 0, s, a);
+hipError_t launch_sort(const StepArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan_counts, dim3((unsigned)a.n_scan1_blocks, (unsigned)a.nsp), dim3(kBlock), 0,
+                     s, a);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)a.n_scan1_blocks + 1u, (unsigned)a.nsp), dim3(kBlock),
+                     0, s, a);
   hipLaunchKernelGGL(k_rank, dim3(8u * (unsigned)a.t.per_xcd, (unsigned)a.nsp), dim3(kBlock),
                      rank_lds_bytes(a.t), s, a);
   return hipGetLastError();
