@@ -122,6 +122,9 @@ def cpu_baseline(wl, budget_s):
                       f"{el:.1f} s"}
 
 
+PROFILE_EVERY = 4
+
+
 def run_gpu(binding, torch, wl, precision, steps, warmup, tile, autotune=False):
     """Load the workload, run warmup cycles (and the tile autotuner, whose cycles come before
     the timed ones), then time `steps` cycles (wall clock around the whole batch, HIP events
@@ -141,7 +144,9 @@ def run_gpu(binding, torch, wl, precision, steps, warmup, tile, autotune=False):
     info0 = ctx.get_info()
     n_alive0 = sum(info0["alive"])
 
-    ctx.profile_enable(True)
+    # kernel times from HIP events on every PROFILE_EVERY-th timed cycle (the events leave the
+    # GPU idle between kernels, so the other cycles run without them)
+    ctx.profile_enable(True, every=PROFILE_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.step(steps)

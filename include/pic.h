@@ -177,8 +177,11 @@ pic_status pic_set_stream(pic_ctx *ctx, void *stream);
 /* Wait until all queued work of the context has finished. */
 pic_status pic_sync(pic_ctx *ctx);
 
-/* Per-kernel timing with HIP events recorded on the context's stream (on = 1 starts a new
- * measurement, 0 stops); read the sums with pic_profile_read (waits for the stream). */
+/* Per-kernel timing with HIP events recorded on the context's stream.  on = n > 0 starts a
+ * new measurement that times every n-th cycle (the first cycle after the call, then every
+ * n-th: each event pair leaves the GPU idle for a few microseconds between kernels, so
+ * n > 1 keeps most cycles free of them); 0 stops; negative is an error.  Read the sums, over
+ * the timed cycles only, with pic_profile_read (waits for the stream). */
 pic_status pic_profile_enable(pic_ctx *ctx, int32_t on);
 pic_status pic_profile_read(pic_ctx *ctx, pic_profile *out);
 

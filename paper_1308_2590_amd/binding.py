@@ -257,8 +257,10 @@ class Context:
     def sync(self):
         self._check(self.lib.pic_sync(self.h))
 
-    def profile_enable(self, on=True):
-        self._check(self.lib.pic_profile_enable(self.h, 1 if on else 0))
+    def profile_enable(self, on=True, every=1):
+        """Start (on) or stop per-kernel event timing; with every = n only every n-th cycle is
+        timed, the first one included."""
+        self._check(self.lib.pic_profile_enable(self.h, int(every) if on else 0))
 
     def profile_read(self):
         p = Profile()

@@ -113,8 +113,8 @@ pic_status rebuild(pic_batch *b) {
     ctr[r] = c->step;
     const pic::GridArgs &g = c->g;
     const int32_t items[6] = {
-        (int32_t)((g.nnodes + pic::kBlock - 1) / pic::kBlock),
-        (int32_t)((g.ncells + pic::kBlock - 1) / pic::kBlock),
+        (int32_t)((g.nnodes + pic::kSolveNodes * pic::kBlock - 1) / (pic::kSolveNodes * pic::kBlock)),
+        (int32_t)((g.ncells + pic::kHCells * pic::kBlock - 1) / (pic::kHCells * pic::kBlock)),
         c->n_scan_blocks * c->S,
         c->S,
         (c->tiles.ntiles + pic::kBlock - 1) / pic::kBlock,

@@ -214,7 +214,7 @@ pic_status redeposit(pic_ctx *c) {
   if (rs != PIC_OK) return rs;
   if ((rs = build_tile_list(c)) != PIC_OK) return rs;
   pic::StepArgs a = step_args(c, false);
-  a.Ebar = c->Ebar;
+  a.Eold = a.Enew = c->E[c->ecur];  // not read by a deposit
   a.Hold = c->H[c->hcur];
   a.Hnew = c->H[c->hcur];
   a.M = c->M;
@@ -277,7 +277,8 @@ StepArgs cycle_step_args(pic_ctx *c, int p) {
   c->cur = p;
   StepArgs a = step_args(c, true);
   c->cur = saved;
-  a.Ebar = c->Ebar;
+  a.Eold = c->E[p];
+  a.Enew = c->E[1 - p];
   a.Hold = c->H[p];
   a.Hnew = c->H[1 - p];
   a.M = c->M;
@@ -293,7 +294,6 @@ FieldArgs cycle_field_args(pic_ctx *c, int p) {
   fa.E = c->E[p];
   fa.H = c->H[p];
   fa.E_new = c->E[1 - p];
-  fa.Ebar = c->Ebar;
   fa.H_new = c->H[1 - p];
   fa.mtile = c->mtile;
   fa.tx = c->tiles.tx;
@@ -391,15 +391,12 @@ pic_status pic_init_grid(const pic_grid_desc *d, pic_ctx **out) {
     if ((st = dalloc(c, &c->E[b], 3 * nn, "alloc E")) != PIC_OK) return bail(st);
     if ((st = dalloc(c, &c->H[b], 3 * nc, "alloc H")) != PIC_OK) return bail(st);
   }
-  if ((st = dalloc(c, &c->Ebar, 3 * nn, "alloc E-bar")) != PIC_OK) return bail(st);
   if ((st = dalloc(c, &c->M, (size_t)g.n_planes * nn, "alloc moments")) != PIC_OK) return bail(st);
   if ((st = dalloc(c, &c->flags, 1, "alloc flags")) != PIC_OK) return bail(st);
   std::vector<double> host(3 * std::max(nn, nc));
   for (int r = 0; r < 3; ++r) std::fill(host.begin() + r * nn, host.begin() + (r + 1) * nn, d->e0[r]);
   e = hipMemcpy(c->E[0], host.data(), 3 * nn * sizeof(double), hipMemcpyHostToDevice);
   if (e != hipSuccess) return bail(hip_fail(c, e, "upload E"));
-  e = hipMemcpy(c->Ebar, host.data(), 3 * nn * sizeof(double), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return bail(hip_fail(c, e, "upload E-bar"));
   for (int r = 0; r < 3; ++r) std::fill(host.begin() + r * nc, host.begin() + (r + 1) * nc, d->h0[r]);
   e = hipMemcpy(c->H[0], host.data(), 3 * nc * sizeof(double), hipMemcpyHostToDevice);
   if (e != hipSuccess) return bail(hip_fail(c, e, "upload H"));
@@ -581,7 +578,7 @@ pic_status pic_step(pic_ctx *c, int32_t nsteps) {
   if (!any) return fail(c, PIC_ERR_STATE, "no particles loaded");
   for (int32_t it = 0; it < nsteps; ++it) {
     ProfEvents *pe = nullptr;
-    if (c->prof_on) {
+    if (c->prof_on && (c->prof_count++ % c->prof_every) == 0) {
       if (c->prof_used == c->prof_ev.size()) {
         if (c->prof_ev.size() >= 4096) {
           HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
@@ -737,11 +734,14 @@ pic_status pic_sync(pic_ctx *c) {
 
 pic_status pic_profile_enable(pic_ctx *c, int32_t on) {
   if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
+  if (on < 0) return fail(c, PIC_ERR_ARG, "on must be >= 0");
   HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
   if (on) {
     c->prof_used = 0;
     c->prof_acc = pic_profile{};
     c->prof_on = true;
+    c->prof_every = on;
+    c->prof_count = 0;
   } else {
     prof_accumulate(c);
     c->prof_on = false;
@@ -769,7 +769,6 @@ void pic_destroy(pic_ctx *c) {
     dfree(c, c->E[b], 3 * nn * sizeof(double));
     dfree(c, c->H[b], 3 * nc * sizeof(double));
   }
-  dfree(c, c->Ebar, 3 * nn * sizeof(double));
   dfree(c, c->M, (size_t)c->g.n_planes * nn * sizeof(double));
   dfree(c, c->flags, sizeof(uint32_t));
   for (int b = 0; b < 2; ++b) {

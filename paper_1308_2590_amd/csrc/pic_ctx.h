@@ -44,7 +44,7 @@ struct pic_ctx {
   int S = 0;
   hipStream_t stream = nullptr;
   hipStream_t own_stream = nullptr;
-  double *E[2] = {}, *Ebar = nullptr, *H[2] = {}, *M = nullptr;
+  double *E[2] = {}, *H[2] = {}, *M = nullptr;
   int ecur = 0, hcur = 0, cur = 0;  // flip together every cycle
   pic::SpeciesState sp[PIC_MAX_SPECIES];
   uint32_t *flags = nullptr;
@@ -60,6 +60,8 @@ struct pic_ctx {
   std::string err;
   // profiling
   bool prof_on = false;
+  int32_t prof_every = 1;  // time every prof_every-th cycle
+  int64_t prof_count = 0;  // cycles since profiling started
   std::vector<pic::ProfEvents> prof_ev;
   size_t prof_used = 0;
   pic_profile prof_acc{};

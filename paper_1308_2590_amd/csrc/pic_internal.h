@@ -13,6 +13,8 @@ constexpr int kMaxSpecies = PIC_MAX_SPECIES;
 constexpr int kMoveCodes = 9;      // destination cell relative to the source: 3 x 3 block
 constexpr uint8_t kAbsorbed = 9;   // move code of a particle that left an absorbing boundary
 constexpr int kBlock = 256;        // threads per block of the tile kernels (4 wavefronts)
+constexpr int kSolveNodes = 2;     // nodes per thread in the E solve
+constexpr int kHCells = 2;         // cells per thread in the H update
 constexpr int kScanItems = 4;      // cells per thread in the count scan
 constexpr int kScanBlock = kBlock * kScanItems;
 constexpr int kScan1Items = 4;      // cells per thread in the scan of a cycle's sort
@@ -69,7 +71,7 @@ struct StepArgs {
   int32_t n_scan_blocks;     // blocks of the count scan per species
   int32_t nsp;               // species slots
   SpeciesArgs sp[kMaxSpecies];
-  const double *Ebar;        // [3][nodes]
+  const double *Eold, *Enew; // E^n, E^{n+1} [3][nodes]: E-bar is their mean
   const double *Hold;        // H^{n+1/2} [3][cells]
   const double *Hnew;        // H^{n+3/2} [3][cells]
   double *M;                 // moment planes [12 + S][nodes]
@@ -93,7 +95,7 @@ struct FieldArgs {
   double *M;                 // moment planes: read, then zeroed, where deposits can be
   const double *E;           // E^n
   const double *H;           // H^{n+1/2}
-  double *E_new, *Ebar, *H_new;
+  double *E_new, *H_new;
   // Deposit flags of the particle tiles (tx x tz cells, ntx per row): a node's moments are
   // read only where the flag of the tile holding the node is set; the H update clears the
   // flags for the next deposit.  NULL: every node is read and cleared.
@@ -113,8 +115,8 @@ struct BatchArgs {
   int64_t *step_ctr;         // [nruns] cycles done (E^n is at step * dt)
   int32_t nruns;
   // exclusive prefix sums over runs ([nruns + 1]) of the work items of each kernel
-  const int32_t *pre_nodes;  // blocks of kBlock nodes
-  const int32_t *pre_cells;  // blocks of kBlock cells
+  const int32_t *pre_nodes;  // blocks of kSolveNodes * kBlock nodes
+  const int32_t *pre_cells;  // blocks of kHCells * kBlock cells
   const int32_t *pre_scan;   // scan blocks x species slots
   const int32_t *pre_spec;   // species slots
   const int32_t *pre_tflag;  // blocks of kBlock tiles

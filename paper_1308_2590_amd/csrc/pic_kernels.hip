@@ -120,11 +120,17 @@ __device__ __forceinline__ void clear_node_moments(const FieldArgs &a, int64_t n
   for (int p = 0; p < a.g.n_planes; ++p) a.M[p * a.g.nnodes + n] = 0.0;
 }
 
-// Eq. (4) at the node (i, k), i an interior column.  Reads S-hat and delta-j of the node where
-// a deposit can have reached it (zero elsewhere) and clears its moment planes; returns E^n of
-// the node in eo.  Every load is issued before the first store (the compiler cannot tell the
-// planes apart, so a load after a store would wait for it).
-__device__ void solve_node(const FieldArgs &a, int i, int k, double eo[3], double out[3]) {
+// Inputs of Eq. (4) at the node (i, k), i an interior column: curl H from the 2x2 cells
+// around the node, E^n, and S-hat and delta-j where a deposit can have reached the node (zero
+// elsewhere).  Loads only: a thread gathers the inputs of all its nodes before its first
+// store (the compiler cannot tell the planes apart, so a load after a store waits for it).
+struct NodeIn {
+  double curl[3], e[3], S[9], J[3];
+  int64_t n;
+  bool dep;
+};
+
+__device__ __forceinline__ void node_load(const FieldArgs &a, int i, int k, NodeIn &in) {
   const GridArgs &g = a.g;
   const int nx = g.nx, nz = g.nz;
   const int64_t nn = g.nnodes, nc = g.ncells;
@@ -137,29 +143,36 @@ __device__ void solve_node(const FieldArgs &a, int i, int k, double eo[3], doubl
   double dHy_dz = ((Hy[cUR] + Hy[cUL]) - (Hy[cDR] + Hy[cDL])) * a.r2dz;
   double dHy_dx = ((Hy[cUR] + Hy[cDR]) - (Hy[cUL] + Hy[cDL])) * a.r2dx;
   double dHz_dx = ((Hz[cUR] + Hz[cDR]) - (Hz[cUL] + Hz[cDL])) * a.r2dx;
-  double curl[3] = {-dHy_dz, dHx_dz - dHz_dx, dHy_dx};
-  int64_t n = (int64_t)k * g.nxn + i;
-  double S[9], J[3], e[3], rhs[3];
+  in.curl[0] = -dHy_dz;
+  in.curl[1] = dHx_dz - dHz_dx;
+  in.curl[2] = dHy_dx;
+  const int64_t n = (int64_t)k * g.nxn + i;
+  in.n = n;
 #pragma unroll
-  for (int r = 0; r < 3; ++r) e[r] = a.E[r * nn + n];
-  const bool dep = node_deposited(a, i, k);
-  if (dep) {
+  for (int r = 0; r < 3; ++r) in.e[r] = a.E[r * nn + n];
+  in.dep = node_deposited(a, i, k);
+  if (in.dep) {
 #pragma unroll
-    for (int r = 0; r < 9; ++r) S[r] = a.M[r * nn + n];
+    for (int r = 0; r < 9; ++r) in.S[r] = a.M[r * nn + n];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) J[r] = a.M[(9 + r) * nn + n];
+    for (int r = 0; r < 3; ++r) in.J[r] = a.M[(9 + r) * nn + n];
   } else {
 #pragma unroll
-    for (int r = 0; r < 9; ++r) S[r] = 0.0;
+    for (int r = 0; r < 9; ++r) in.S[r] = 0.0;
 #pragma unroll
-    for (int r = 0; r < 3; ++r) J[r] = 0.0;
+    for (int r = 0; r < 3; ++r) in.J[r] = 0.0;
   }
-#pragma unroll
-  for (int r = 0; r < 3; ++r) eo[r] = e[r];
+}
+
+// Eq. (4): E^{n+1} = (I + S)^{-1} [(I - S) E^n + dt (curl H - delta-j)].
+__device__ __forceinline__ void node_solve(const FieldArgs &a, const NodeIn &in, double out[3]) {
+  const double dt = a.g.dt;
+  const double *S = in.S, *e = in.e;
+  double rhs[3];
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
     double se = S[3 * r] * e[0] + S[3 * r + 1] * e[1] + S[3 * r + 2] * e[2];
-    rhs[r] = (e[r] - se) + g.dt * (curl[r] - J[r]);
+    rhs[r] = (e[r] - se) + dt * (in.curl[r] - in.J[r]);
   }
   double A[9];
 #pragma unroll
@@ -179,18 +192,14 @@ __device__ void solve_node(const FieldArgs &a, int i, int k, double eo[3], doubl
   out[0] = (c00 * rhs[0] + c10 * rhs[1] + c20 * rhs[2]) * rdet;
   out[1] = (c01 * rhs[0] + c11 * rhs[1] + c21 * rhs[2]) * rdet;
   out[2] = (c02 * rhs[0] + c12 * rhs[1] + c22 * rhs[2]) * rdet;
-  if (dep) clear_node_moments(a, n);
 }
 
-// E^{n+1} and E-bar = (E^n + E^{n+1}) / 2 of node n.
-__device__ __forceinline__ void write_e(const FieldArgs &a, int64_t n, const double eo[3],
-                                        const double en[3]) {
+// E^{n+1} of node n.  (The particle kernel forms E-bar = (E^n + E^{n+1}) / 2 where it reads
+// the fields.)
+__device__ __forceinline__ void write_e(const FieldArgs &a, int64_t n, const double en[3]) {
   const int64_t nn = a.g.nnodes;
 #pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    a.E_new[r * nn + n] = en[r];
-    a.Ebar[r * nn + n] = 0.5 * (eo[r] + en[r]);
-  }
+  for (int r = 0; r < 3; ++r) a.E_new[r * nn + n] = en[r];
 }
 
 // Mur boundary (Step 3) at the column i = 0 or i = nx of an absorbing axis, from E^n (eo_in)
@@ -223,59 +232,108 @@ __device__ void mur_node(const FieldArgs &a, double tE, int i, int k, const doub
       en[r] = Eo_in + kappa * (ein[r] - Eo_b);
     }
   }
-  write_e(a, nb, eo, en);
+  write_e(a, nb, en);
   // the boundary node takes deposits too; its planes are not used by the solve
   if (node_deposited(a, i, k)) clear_node_moments(a, nb);
 }
 
-// One node of the E solve.  On an absorbing axis the thread of the inner column next to a
-// boundary column also writes that boundary column, so every node's moments are read and
-// cleared by a single thread (an absorbing axis has nx >= 2).
-__device__ __forceinline__ void solve_e_body(const FieldArgs &a, double tE, int64_t n) {
+// Nodes n0, n0 + stride, ... of the E solve (kSolveNodes per thread, their inputs loaded
+// together).  On an absorbing axis the thread of the inner column next to a boundary column
+// also writes that column, so every node's moments are read and cleared by a single thread (an
+// absorbing axis has nx >= 2).
+
+__device__ __forceinline__ void solve_e_body(const FieldArgs &a, double tE, int64_t n0,
+                                             int64_t stride) {
   const GridArgs &g = a.g;
-  if (n >= g.nnodes) return;
-  const int k = (int)(n / g.nxn), i = (int)(n - (int64_t)k * g.nxn);
   const bool absorbing = g.bc_x == PIC_BC_ABSORBING;
-  if (absorbing && (i == 0 || i == g.nx)) return;
-  double eo[3], en[3];
-  solve_node(a, i, k, eo, en);
-  write_e(a, n, eo, en);
-  if (absorbing) {
-    if (i == 1) mur_node(a, tE, 0, k, eo, en);
-    if (i == g.nx - 1) mur_node(a, tE, g.nx, k, eo, en);
+  NodeIn in[kSolveNodes];
+  bool live[kSolveNodes];
+  int ii[kSolveNodes], kk[kSolveNodes];
+#pragma unroll
+  for (int q = 0; q < kSolveNodes; ++q) {
+    const int64_t n = n0 + q * stride;
+    const int k = (int)(n / g.nxn), i = (int)(n - (int64_t)k * g.nxn);
+    ii[q] = i;
+    kk[q] = k;
+    live[q] = n < g.nnodes && !(absorbing && (i == 0 || i == g.nx));
+    if (live[q]) node_load(a, i, k, in[q]);
+  }
+  double en[kSolveNodes][3];
+#pragma unroll
+  for (int q = 0; q < kSolveNodes; ++q)
+    if (live[q]) node_solve(a, in[q], en[q]);
+#pragma unroll
+  for (int q = 0; q < kSolveNodes; ++q) {
+    if (!live[q]) continue;
+    if (in[q].dep) clear_node_moments(a, in[q].n);
+    write_e(a, in[q].n, en[q]);
+    if (absorbing) {
+      if (ii[q] == 1) mur_node(a, tE, 0, kk[q], in[q].e, en[q]);
+      if (ii[q] == g.nx - 1) mur_node(a, tE, g.nx, kk[q], in[q].e, en[q]);
+    }
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_solve_e(const FieldArgs a) {
-  solve_e_body(a, a.t, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+// Block b of a grid of 8 * per blocks runs on XCD b % 8 (round-robin dispatch); give the
+// blocks of one XCD a contiguous band of the grid, so the neighbouring rows a stencil reads
+// are mostly in the same L2.  Returns -1 for the padding blocks.
+__device__ __forceinline__ int64_t xcd_band_block(int64_t nblocks) {
+  const int64_t per = (nblocks + 7) >> 3;
+  const int64_t b = blockIdx.x;
+  const int64_t idx = (b & 7) * per + (b >> 3);
+  return idx < nblocks ? idx : -1;
 }
 
-__device__ __forceinline__ void update_h_body(const FieldArgs &a, int64_t c) {
+__global__ __launch_bounds__(kBlock) void k_solve_e(const FieldArgs a, int64_t nblocks) {
+  const int64_t blk = xcd_band_block(nblocks);
+  if (blk < 0) return;
+  solve_e_body(a, a.t, blk * (kSolveNodes * kBlock) + threadIdx.x, kBlock);
+}
+
+// Cells c0, c0 + stride, ... of the H update (kHCells per thread, all loads before the
+// stores).
+__device__ __forceinline__ void update_h_body(const FieldArgs &a, int64_t c0, int64_t stride) {
   const GridArgs &g = a.g;
-  if (c >= g.ncells) return;
   const int nx = g.nx, nz = g.nz, nxn = g.nxn;
-  int k = (int)(c / nx), i = (int)(c - (int64_t)k * nx);
-  int i1 = (g.bc_x == PIC_BC_PERIODIC) ? wrap1(i + 1, nx) : i + 1;
-  int k1 = wrap1(k + 1, nz);
   const int64_t nn = g.nnodes, nc = g.ncells;
-  int64_t na = (int64_t)k * nxn + i, nb = (int64_t)k * nxn + i1;
-  int64_t ncn = (int64_t)k1 * nxn + i, nd = (int64_t)k1 * nxn + i1;
   const double *Ex = a.E_new, *Ey = a.E_new + nn, *Ez = a.E_new + 2 * nn;
-  double dEx_dz = ((Ex[ncn] + Ex[nd]) - (Ex[na] + Ex[nb])) * a.r2dz;
-  double dEy_dz = ((Ey[ncn] + Ey[nd]) - (Ey[na] + Ey[nb])) * a.r2dz;
-  double dEy_dx = ((Ey[nb] + Ey[nd]) - (Ey[na] + Ey[ncn])) * a.r2dx;
-  double dEz_dx = ((Ez[nb] + Ez[nd]) - (Ez[na] + Ez[ncn])) * a.r2dx;
-  const double h0 = a.H[c], h1 = a.H[nc + c], h2 = a.H[2 * nc + c];  // loaded before any store
-  a.H_new[c] = h0 - g.dt * (-dEy_dz);
-  a.H_new[nc + c] = h1 - g.dt * (dEx_dz - dEz_dx);
-  a.H_new[2 * nc + c] = h2 - g.dt * dEy_dx;
-  // The E solve has read the deposit flags: clear them for the next deposit (one thread per
-  // tile, the one of its first cell).
-  if (a.mtile && i % a.tx == 0 && k % a.tz == 0) a.mtile[(k / a.tz) * a.ntx + i / a.tx] = 0;
+  double hn[kHCells][3];
+  bool live[kHCells];
+#pragma unroll
+  for (int q = 0; q < kHCells; ++q) {
+    const int64_t c = c0 + q * stride;
+    live[q] = c < nc;
+    if (!live[q]) continue;
+    int k = (int)(c / nx), i = (int)(c - (int64_t)k * nx);
+    int i1 = (g.bc_x == PIC_BC_PERIODIC) ? wrap1(i + 1, nx) : i + 1;
+    int k1 = wrap1(k + 1, nz);
+    int64_t na = (int64_t)k * nxn + i, nb = (int64_t)k * nxn + i1;
+    int64_t ncn = (int64_t)k1 * nxn + i, nd = (int64_t)k1 * nxn + i1;
+    double dEx_dz = ((Ex[ncn] + Ex[nd]) - (Ex[na] + Ex[nb])) * a.r2dz;
+    double dEy_dz = ((Ey[ncn] + Ey[nd]) - (Ey[na] + Ey[nb])) * a.r2dz;
+    double dEy_dx = ((Ey[nb] + Ey[nd]) - (Ey[na] + Ey[ncn])) * a.r2dx;
+    double dEz_dx = ((Ez[nb] + Ez[nd]) - (Ez[na] + Ez[ncn])) * a.r2dx;
+    hn[q][0] = a.H[c] - g.dt * (-dEy_dz);
+    hn[q][1] = a.H[nc + c] - g.dt * (dEx_dz - dEz_dx);
+    hn[q][2] = a.H[2 * nc + c] - g.dt * dEy_dx;
+  }
+#pragma unroll
+  for (int q = 0; q < kHCells; ++q) {
+    if (!live[q]) continue;
+    const int64_t c = c0 + q * stride;
+    a.H_new[c] = hn[q][0];
+    a.H_new[nc + c] = hn[q][1];
+    a.H_new[2 * nc + c] = hn[q][2];
+    // The E solve has read the deposit flags: clear them for the next deposit (there are no
+    // more tiles than cells).
+    if (a.mtile && c < (int64_t)a.ntx * ((g.nz + a.tz - 1) / a.tz)) a.mtile[c] = 0;
+  }
 }
 
-__global__ __launch_bounds__(kBlock) void k_update_h(const FieldArgs a) {
-  update_h_body(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+__global__ __launch_bounds__(kBlock) void k_update_h(const FieldArgs a, int64_t nblocks) {
+  const int64_t blk = xcd_band_block(nblocks);
+  if (blk < 0) return;
+  update_h_body(a, blk * (kHCells * kBlock) + threadIdx.x, kBlock);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -573,7 +631,8 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
       if (g.bc_x == PIC_BC_PERIODIC) gi = wrap_any(gi, g.nx); else in = gi <= g.nx;
       const int64_t n = (int64_t)gk * g.nxn + gi;
 #pragma unroll
-      for (int q = 0; q < 3; ++q) Eb[q * Lo.EPL + e] = in ? (T)a.Ebar[q * nn + n] : T(0);
+      for (int q = 0; q < 3; ++q)
+        Eb[q * Lo.EPL + e] = in ? (T)(0.5 * (a.Eold[q * nn + n] + a.Enew[q * nn + n])) : T(0);
     }
     for (int e = threadIdx.x; e < Lo.NPL; e += blockDim.x) {
       const int lk = e / Lo.NW, li = e - lk * Lo.NW;
@@ -1174,12 +1233,14 @@ __device__ __forceinline__ void rank_body(const StepArgs &a, int tile, int speci
       const int rb = rowcs[0], re = rowcs[cw];
       const int jb = rb + (int)((int64_t)(re - rb) * part / wpr);
       const int je = rb + (int)((int64_t)(re - rb) * (part + 1) / wpr);
+      int clb = 0;  // the cell of the next group's first slot, or a cell before it
       if (part > 0 && jb < je) {
         int lo = 0, hi = cw - 1;  // the cell holding slot jb
         while (lo < hi) {
           const int mid = (lo + hi + 1) >> 1;
           if (rowcs[mid] <= jb) lo = mid; else hi = mid - 1;
         }
+        clb = lo;
         int before[kMoveCodes] = {};
         for (int b0 = rowcs[lo]; b0 < jb; b0 += 64) {
           const int j = b0 + lane;
@@ -1197,6 +1258,7 @@ __device__ __forceinline__ void rank_body(const StepArgs &a, int tile, int speci
       // the row's move codes are loaded kGroups groups of 64 at a time (indices clamped into
       // the row), then ranked group by group
       constexpr int kGroups = 8;
+      constexpr int kProbe = 4;
       for (int b0 = jb; b0 < je; b0 += 64 * kGroups) {
         uint32_t lcs[kGroups];
 #pragma unroll
@@ -1208,16 +1270,28 @@ __device__ __forceinline__ void rank_body(const StepArgs &a, int tile, int speci
           const int j = base + lane;
           const bool act = j < je;
           int d = kAbsorbed, cl = 0, loc = 0;
+          // the largest cl with rowcs[cl] <= j: the group's slots are consecutive, so it is
+          // one of the few cells after clb (independent probes, one LDS round trip); a lane
+          // past them searches
+          {
+            int cnt = 0;
+#pragma unroll
+            for (int t = 1; t <= kProbe; ++t) cnt += (clb + t < cw && rowcs[min(clb + t, cw)] <= j) ? 1 : 0;
+            cl = clb + cnt;
+            if (act && cnt == kProbe && cl + 1 < cw && rowcs[cl + 1] <= j) {
+              int lo = cl + 1, hi = cw - 1;
+              while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (rowcs[mid] <= j) lo = mid; else hi = mid - 1;
+              }
+              cl = lo;
+            }
+            clb = __shfl(cl, min(63, je - 1 - base), 64);  // cell of the group's last slot
+          }
           if (act) {
             const uint32_t lc = lcs[q];
             d = (int)(lc & 15u);
             loc = (int)(lc >> 4);
-            int lo = 0, hi = cw - 1;  // largest cl with rowcs[cl] <= j
-            while (lo < hi) {
-              const int mid = (lo + hi + 1) >> 1;
-              if (rowcs[mid] <= j) lo = mid; else hi = mid - 1;
-            }
-            cl = lo;
           }
           const bool valid = act && d < kMoveCodes;
           // The group's slots are in cell order, so the lanes of one cell are contiguous:
@@ -1475,7 +1549,7 @@ __global__ __launch_bounds__(kBlock) void kb_solve_e(const BatchArgs b) {
     const int r = find_run(b.pre_nodes, b.nruns, w);
     const FieldArgs &fa = run_field(b, r);
     const double tE = (double)b.step_ctr[r] * fa.g.dt;
-    solve_e_body(fa, tE, (int64_t)(w - b.pre_nodes[r]) * kBlock + threadIdx.x);
+    solve_e_body(fa, tE, (int64_t)(w - b.pre_nodes[r]) * (kSolveNodes * kBlock) + threadIdx.x, kBlock);
   }
 }
 
@@ -1483,7 +1557,7 @@ __global__ __launch_bounds__(kBlock) void kb_update_h(const BatchArgs b) {
   const int total = b.pre_cells[b.nruns];
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
     const int r = find_run(b.pre_cells, b.nruns, w);
-    update_h_body(run_field(b, r), (int64_t)(w - b.pre_cells[r]) * kBlock + threadIdx.x);
+    update_h_body(run_field(b, r), (int64_t)(w - b.pre_cells[r]) * (kHCells * kBlock) + threadIdx.x, kBlock);
   }
 }
 
@@ -1615,10 +1689,10 @@ size_t rank_lds_bytes(const TileArgs &t) {
 }
 
 hipError_t launch_field_solve(const FieldArgs &a, hipStream_t s) {
-  const int64_t nb_nodes = (a.g.nnodes + kBlock - 1) / kBlock;
-  const int64_t nb_cells = (a.g.ncells + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_solve_e, dim3((unsigned)nb_nodes), dim3(kBlock), 0, s, a);
-  hipLaunchKernelGGL(k_update_h, dim3((unsigned)nb_cells), dim3(kBlock), 0, s, a);
+  const int64_t nb_nodes = (a.g.nnodes + kSolveNodes * kBlock - 1) / (kSolveNodes * kBlock);
+  const int64_t nb_cells = (a.g.ncells + kHCells * kBlock - 1) / (kHCells * kBlock);
+  hipLaunchKernelGGL(k_solve_e, dim3(8u * (unsigned)((nb_nodes + 7) / 8)), dim3(kBlock), 0, s, a, nb_nodes);
+  hipLaunchKernelGGL(k_update_h, dim3(8u * (unsigned)((nb_cells + 7) / 8)), dim3(kBlock), 0, s, a, nb_cells);
   return hipGetLastError();
 }
 

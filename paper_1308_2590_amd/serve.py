@@ -25,7 +25,7 @@ def footprint_bytes(nx, nz, bc_x, n_species, n_particles, precision):
     """Device bytes a run will hold (the library's allocations, rounded up by 10 %)."""
     nxn = nx + (1 if bc_x == 1 else 0)
     nodes, cells = nxn * nz, nx * nz
-    grid = 8 * nodes * (3 * 3 + 12 + n_species) + 8 * cells * 3 * 2
+    grid = 8 * nodes * (3 * 2 + 12 + n_species) + 8 * cells * 3 * 2
     per_species_cells = 4 * cells * (9 + 1 + 2) + 8
     per_particle = 2 * (24 if precision == 1 else 40) + 2 * 4 + 4
     tiles = 4 * cells  # tile flags, lists and maps, generously

@@ -267,6 +267,28 @@ def test_argument_errors(pic):
     big.close()
 
 
+def test_profile_sampling(pic):
+    """profile_enable(every=n) times the first cycle and every n-th after it; the sums count
+    the timed cycles only; a negative argument is refused."""
+    wl = SMALL[0]
+    ctx = pic.Context(wl.grid)
+    for s, sp in enumerate(wl.species):
+        ctx.load_particles(s, sp.q, sp.m, sp.w, sp.xi_x, sp.xi_z, sp.ux, sp.uy, sp.uz)
+    ctx.profile_enable(True, every=3)
+    ctx.step(7)
+    p = ctx.profile_read()
+    assert p["steps"] == 3 and p["particle_launches"] == 3
+    assert p["step_ms"] > 0 and p["particle_ms"] > 0
+    ctx.profile_enable(True)
+    ctx.step(2)
+    assert ctx.profile_read()["steps"] == 2
+    ctx.profile_enable(False)
+    with pytest.raises(pic.PicError) as e:
+        ctx._check(ctx.lib.pic_profile_enable(ctx.h, -2))
+    assert e.value.status == 1
+    ctx.close()
+
+
 def test_tile_size_invariance(pic):
     """The result does not depend on the tile decomposition (only on summation order)."""
     wl = picgen.random_small(5, nx=37, nz=29, ppc=6, bc_x=1, dx=0.5, dz=0.5, dt=0.4)
