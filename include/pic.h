@@ -142,7 +142,8 @@ pic_status pic_load_fields(pic_ctx *ctx, const double *e, const double *h);
 /* Change the tile shape (cells per particle tile; 0, 0 picks it from the particles per
  * occupied cell).  The tiling only distributes work: results are unchanged up to the order of
  * floating-point atomic additions.  Waits for the stream.  Errors: PIC_ERR_ARG (sizes outside
- * 1..64, or the tile's LDS accumulators would exceed 64 KiB; the old shape is kept),
+ * 1..64, or the tile's LDS accumulators would exceed the LDS a block may use on the device;
+ * the old shape is kept),
  * PIC_ERR_STATE (no particles loaded). */
 pic_status pic_set_tiles(pic_ctx *ctx, int32_t tile_x, int32_t tile_z);
 

@@ -88,7 +88,7 @@ bool mixed(const pic_ctx *c) { return c->d.precision == PIC_PREC_MIXED; }
 // Tile size from the load.  One wavefront handles one row of a tile, each lane a contiguous
 // run of that row's particles, so a tile is 4 rows high and wide enough for a row to hold
 // about 1024 particles of a species (runs of ~16); a power of two in [4, 32], shrunk until
-// the LDS accumulators fit in 64 KiB.
+// the LDS accumulators fit in 64 KiB (two blocks per CU).
 void choose_tiles(pic_ctx *c, int64_t total, int64_t occupied, int nspecies) {
   int tx = c->d.tile_x, tz = c->d.tile_z;
   if (tx <= 0 || tz <= 0) {
@@ -243,8 +243,8 @@ pic_status retile(pic_ctx *c) {
   int64_t occupied = 0;
   for (uint8_t o : occ) occupied += o;
   choose_tiles(c, total, occupied, nloaded);
-  if (pic::particle_lds_bytes(c->g, c->tiles, mixed(c)) > 65536)
-    return fail(c, PIC_ERR_ARG, "tile too large: its LDS accumulators exceed 64 KiB");
+  if (pic::particle_lds_bytes(c->g, c->tiles, mixed(c)) > c->lds_max)
+    return fail(c, PIC_ERR_ARG, "tile too large: its LDS accumulators exceed the LDS of a block");
   return PIC_OK;
 }
 
@@ -353,9 +353,13 @@ pic_status pic_init_grid(const pic_grid_desc *d, pic_ctx **out) {
   if (d->device < 0 || d->device >= ndev) return fail(nullptr, PIC_ERR_ARG, "device ordinal out of range");
   e = hipSetDevice(d->device);
   if (e != hipSuccess) return fail(nullptr, PIC_ERR_DEVICE, "hipSetDevice failed");
+  int lds_max = 0;
+  e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, d->device);
+  if (e != hipSuccess || lds_max <= 0) return fail(nullptr, PIC_ERR_DEVICE, "cannot read the LDS size");
 
   pic_ctx *c = new pic_ctx();
   c->d = *d;
+  c->lds_max = (size_t)lds_max;
   c->S = d->n_species;
   pic::GridArgs &g = c->g;
   g.nx = d->nx;

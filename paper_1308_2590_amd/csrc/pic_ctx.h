@@ -55,6 +55,7 @@ struct pic_ctx {
   int32_t *col_tile = nullptr, *row_tile = nullptr;  // cell column / row -> tile index
   int64_t step = 0;
   int64_t bytes = 0;
+  size_t lds_max = 65536;  // LDS a block may use on the context's device
   int32_t n_scan_blocks = 0;
   int32_t n_scan1_blocks = 0;  // blocks of the scan of a cycle's sort
   std::string err;

@@ -381,26 +381,27 @@ __device__ __forceinline__ Compact<T> compact_moments(const SpConst<T> &k, T gin
   return m;
 }
 
-// Add one corner's share (weight W) of compact moments to the 13 LDS moment planes at node o,
-// expanding S-hat with the cell's B.  The expansion runs in the kernel's arithmetic type; the
-// LDS accumulators are FP64 in both precisions (FP32 LDS atomic adds are far slower than FP64
-// ones on gfx950).
+// Add one corner's share of compact moments (one particle's, weighted, or a lane's sum):
+// delta-j and the density to the node planes at node o, and the three S-hat scalars to the
+// planes of that corner of cell rc.  S-hat is expanded with each cell's B only when the tile is
+// folded, so a flush does no arithmetic.  The LDS accumulators are FP64 in both precisions
+// (FP32 LDS atomic adds are far slower than FP64 ones on gfx950).
+struct AccLds {
+  double *node;  // [3 + species][plane]: delta-j x, y, z, then one density plane per species
+  double *cell;  // [3 scalars][4 corners][npl]: S-hat scalars a0, a1, a2 per cell corner
+  int plane, npl, LW, NW;
+};
+
 template <typename T>
-__device__ __forceinline__ void expand_add(double *acc, int plane, int o, T A0, T A1, T A2, T J0,
-                                           T J1, T J2, T D, int dens_plane, T B0, T B1, T B2) {
-  atomicAdd(&acc[0 * plane + o], (double)fmaT(A2, B0 * B0, A0));
-  atomicAdd(&acc[1 * plane + o], (double)fmaT(A2, B0 * B1, A1 * B2));
-  atomicAdd(&acc[2 * plane + o], (double)fmaT(A2, B0 * B2, -A1 * B1));
-  atomicAdd(&acc[3 * plane + o], (double)fmaT(A2, B1 * B0, -A1 * B2));
-  atomicAdd(&acc[4 * plane + o], (double)fmaT(A2, B1 * B1, A0));
-  atomicAdd(&acc[5 * plane + o], (double)fmaT(A2, B1 * B2, A1 * B0));
-  atomicAdd(&acc[6 * plane + o], (double)fmaT(A2, B2 * B0, A1 * B1));
-  atomicAdd(&acc[7 * plane + o], (double)fmaT(A2, B2 * B1, -A1 * B0));
-  atomicAdd(&acc[8 * plane + o], (double)fmaT(A2, B2 * B2, A0));
-  atomicAdd(&acc[9 * plane + o], (double)J0);
-  atomicAdd(&acc[10 * plane + o], (double)J1);
-  atomicAdd(&acc[11 * plane + o], (double)J2);
-  atomicAdd(&acc[dens_plane * plane + o], (double)D);
+__device__ __forceinline__ void corner_add(const AccLds &A, int o, int rc, int corner, T A0, T A1,
+                                           T A2, T J0, T J1, T J2, T D, int dplane) {
+  atomicAdd(&A.node[0 * A.plane + o], (double)J0);
+  atomicAdd(&A.node[1 * A.plane + o], (double)J1);
+  atomicAdd(&A.node[2 * A.plane + o], (double)J2);
+  atomicAdd(&A.node[dplane * A.plane + o], (double)D);
+  atomicAdd(&A.cell[(0 * 4 + corner) * A.npl + rc], (double)A0);
+  atomicAdd(&A.cell[(1 * 4 + corner) * A.npl + rc], (double)A1);
+  atomicAdd(&A.cell[(2 * 4 + corner) * A.npl + rc], (double)A2);
 }
 
 // Per-lane running sum of the compact moments of consecutive particles that stay in one
@@ -428,22 +429,21 @@ struct CellAcc {
       D[c] = fmaT(W[c], w, D[c]);
     }
   }
-  // B is the field of the accumulated cell, whose lower-left node is (cell + 1, lz) locally.
-  __device__ __forceinline__ void flush(double *acc, int plane, int LW, int lz, int dens_plane,
-                                        T B0, T B1, T B2) {
-    const int b = lz * LW + cell + 1;
+  // The accumulated cell is (cell, lz - 1) of the tile: ring cell (cell + 1, lz), whose
+  // lower-left node is (cell + 1, lz) locally.
+  __device__ __forceinline__ void flush(const AccLds &acc, int lz, int dplane) {
+    const int b = lz * acc.LW + cell + 1, rc = lz * acc.NW + cell + 1;
 #pragma unroll
     for (int c = 0; c < 4; ++c)
-      expand_add(acc, plane, b + (c & 1) + (c >> 1) * LW, A0[c], A1[c], A2[c], J0[c], J1[c],
-                 J2[c], D[c], dens_plane, B0, B1, B2);
+      corner_add(acc, b + (c & 1) + (c >> 1) * acc.LW, rc, c, A0[c], A1[c], A2[c], J0[c], J1[c],
+                 J2[c], D[c], dplane);
   }
   // End of a row: every lane flushes at once, and the lanes whose runs end in one cell are
   // neighbours.  Their sums are first added up across lanes (a segmented reduction with
   // shuffles towards the first lane of each cell), so that one lane per cell issues the LDS
   // atomics; same-address atomics from many lanes of one instruction are serialised.  All 64
   // lanes must be active.
-  __device__ __forceinline__ void flush_row_end(double *acc, int plane, int LW, int lz,
-                                                int dens_plane, T B0, T B1, T B2, int lane) {
+  __device__ __forceinline__ void flush_row_end(const AccLds &acc, int lz, int dplane, int lane) {
     const int prev = __shfl_up(cell, 1);
     const bool head = lane == 0 || prev != cell;
     const uint64_t heads = __ballot(head);
@@ -464,7 +464,7 @@ struct CellAcc {
         v = __shfl_down(D[c], d); D[c] += take ? v : T(0);
       }
     }
-    if (head && cell >= 0) flush(acc, plane, LW, lz, dens_plane, B0, B1, B2);
+    if (head && cell >= 0) flush(acc, lz, dplane);
   }
 };
 
@@ -476,41 +476,41 @@ constexpr int kMqWords = 8;  // fx fz a0 a1 a2 j0 j1 j2
 template <typename T>
 struct MoverQ {
   T *v;      // [kMqWords][kMqCap]
-  int *idx;  // [2][kMqCap]: accumulator node index, H^{n+3/2} index
+  int *idx;  // [2][kMqCap]: lower-left accumulator node, ring cell of the destination
 };
 
 template <typename T>
-__device__ __forceinline__ void drain_movers(const MoverQ<T> &q, int count, int lane, double *acc,
-                                             int plane, int LW, int dens_plane, T w, const T *Hn,
-                                             int NPL) {
+__device__ __forceinline__ void drain_movers(const MoverQ<T> &q, int count, int lane,
+                                             const AccLds &acc, int dplane, T w) {
   if (lane < count) {
     const T fx = q.v[0 * kMqCap + lane], fz = q.v[1 * kMqCap + lane];
     const T a0 = q.v[2 * kMqCap + lane], a1 = q.v[3 * kMqCap + lane];
     const T a2 = q.v[4 * kMqCap + lane], j0 = q.v[5 * kMqCap + lane];
     const T j1 = q.v[6 * kMqCap + lane], j2 = q.v[7 * kMqCap + lane];
-    const int o = q.idx[lane], hn = q.idx[kMqCap + lane];
-    const T B0 = Hn[hn], B1 = Hn[NPL + hn], B2 = Hn[2 * NPL + hn];
+    const int o = q.idx[lane], rc = q.idx[kMqCap + lane];
 #pragma unroll 1
     for (int c = 0; c < 4; ++c) {
       const int cx = c & 1, cz = c >> 1;
       const T W = (cx ? fx : T(1) - fx) * (cz ? fz : T(1) - fz);
-      expand_add(acc, plane, o + cx + cz * LW, W * a0, W * a1, W * a2, W * j0, W * j1, W * j2,
-                 W * w, dens_plane, B0, B1, B2);
+      corner_add(acc, o + cx + cz * acc.LW, rc, c, W * a0, W * a1, W * a2, W * j0, W * j1, W * j2,
+                 W * w, dplane);
     }
   }
 }
 
 // LDS layout of the particle kernel (byte offsets): the moment accumulators of the tile and its
-// halo, the fields the tile's particles read (E-bar on the tile's nodes, H^{n+1/2} on its
-// cells, H^{n+3/2} on its cells plus a one-cell ring), the per-wave mover queues, and the int
-// move counters, and the arrival counts of the tile's cells and their one-cell ring.
-// Accumulators are FP64; fields and queues use the kernel's arithmetic type.
+// halo (delta-j and density per node, S-hat scalars per corner of the tile's cells and their
+// one-cell ring), the fields the tile's particles read (E-bar on the tile's nodes, H^{n+1/2} on
+// its cells, H^{n+3/2} on its cells plus the ring), the per-wave mover queues, the int move
+// counters, and the arrival counts of the tile's cells and their ring.  Accumulators are FP64;
+// fields and queues use the kernel's arithmetic type.
 struct TileLds {
   int LW, LH, plane;          // accumulator node grid (tx + 3) x (tz + 3)
   int EW, EPL;                // E-bar node grid (tx + 1) x (tz + 1)
   int HPL;                    // H^{n+1/2} cells tx x tz
   int NW, NPL;                // H^{n+3/2} cells (tx + 2) x (tz + 2)
-  size_t acc, eb, ho, hn, mq, cnt, arr;  // byte offsets
+  int n_node;                 // node accumulator planes: 3 + species
+  size_t acc, accc, eb, ho, hn, mq, cnt, arr;  // byte offsets
   size_t bytes;
   __host__ __device__ TileLds(int n_planes, int tx, int tz, int tsize) {
     LW = tx + 3;
@@ -521,8 +521,10 @@ struct TileLds {
     HPL = tx * tz;
     NW = tx + 2;
     NPL = NW * (tz + 2);
+    n_node = 3 + (n_planes - 12);
     acc = 0;
-    eb = acc + (size_t)n_planes * plane * sizeof(double);
+    accc = acc + (size_t)n_node * plane * sizeof(double);
+    eb = accc + (size_t)12 * NPL * sizeof(double);
     ho = eb + 3 * (size_t)EPL * tsize;
     hn = ho + 3 * (size_t)HPL * tsize;
     mq = (hn + 3 * (size_t)NPL * tsize + 7) & ~(size_t)7;
@@ -604,15 +606,17 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
   extern __shared__ double lds[];
   char *ldsb = reinterpret_cast<char *>(lds);
   const TileLds Lo(g.n_planes, t.tx, t.tz, (int)sizeof(T));
-  double *acc = reinterpret_cast<double *>(ldsb + Lo.acc);
+  const AccLds acc{reinterpret_cast<double *>(ldsb + Lo.acc),
+                   reinterpret_cast<double *>(ldsb + Lo.accc), Lo.plane, Lo.NPL, Lo.LW, Lo.NW};
   T *Eb = reinterpret_cast<T *>(ldsb + Lo.eb);
   T *Ho = reinterpret_cast<T *>(ldsb + Lo.ho);
   T *Hn = reinterpret_cast<T *>(ldsb + Lo.hn);
   int *cntL = reinterpret_cast<int *>(ldsb + Lo.cnt);
   int *arrL = reinterpret_cast<int *>(ldsb + Lo.arr);
   const int LW = Lo.LW, plane = Lo.plane;
+  const int n_acc = Lo.n_node * plane + 12 * Lo.NPL;  // node planes, then cell-corner planes
 
-  for (int e = threadIdx.x; e < g.n_planes * plane; e += blockDim.x) acc[e] = 0.0;
+  for (int e = threadIdx.x; e < n_acc; e += blockDim.x) acc.node[e] = 0.0;
   // stage the fields of the tile
   for (int e = threadIdx.x; e < Lo.HPL; e += blockDim.x) {
     const int lk = e / t.tx, li = e - lk * t.tx;
@@ -667,7 +671,7 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
     const SpConst<T> K{(T)sp.beta, (T)sp.cS, (T)sp.kJ, (T)sp.w};
     const typename Pstate<MIXED>::Src src(sp);
     const int32_t *perm = sp.perm;
-    const int dens = 12 + s;
+    const int dplane = 3 + s;  // density plane of the species in the node accumulators
     // A tile with fewer rows than wavefronts splits each row's particles into wpr contiguous
     // parts, one per wavefront, so short tiles keep every wavefront busy.
     const int nrows = k1 - k0;
@@ -691,9 +695,8 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
       ca.cell = -1;
       int nq = 0;  // movers queued by this wavefront (uniform)
       // fields of the cell the lane's run is in, kept in registers while the run stays in it:
-      // H^{n+1/2} (fB, the push), E-bar at its 4 nodes (fE), and the field the deposit expands
-      // S-hat with (fD: H^{n+3/2} after a push, H^{n+1/2} for a deposit of the current state)
-      T fB0 = T(0), fB1 = T(0), fB2 = T(0), fE[12], fD0 = T(0), fD1 = T(0), fD2 = T(0);
+      // H^{n+1/2} (fB) and E-bar at its 4 nodes (fE, the push)
+      T fB0 = T(0), fB1 = T(0), fB2 = T(0), fE[12];
       // The run is processed in chunks of kChunk particles: the chunk's state loads are issued
       // together (with the next chunk's permutation entries), then its particles are pushed
       // from registers in an unrolled sequence.  Global stores share the vector-memory counter
@@ -752,7 +755,6 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
           // cell's accumulator.  LDS operations complete in order, so a read issued after the
           // flush's atomics (or consumed while they are in flight) would wait for all of them.
           const bool newcell = ok && li != ca.cell;
-          const T oD0 = fD0, oD1 = fD1, oD2 = fD2;
           if (newcell) {
             fB0 = Ho[hc];
             fB1 = Ho[Lo.HPL + hc];
@@ -767,14 +769,6 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
                 fE[4 * qq + 2] = f[Lo.EW];
                 fE[4 * qq + 3] = f[Lo.EW + 1];
               }
-              const int h0 = (lk + 1) * Lo.NW + li + 1;
-              fD0 = Hn[h0];
-              fD1 = Hn[Lo.NPL + h0];
-              fD2 = Hn[2 * Lo.NPL + h0];
-            } else {
-              fD0 = fB0;
-              fD1 = fB1;
-              fD2 = fB2;
             }
           }
           const T one = T(1);
@@ -782,7 +776,7 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
           if (!PUSH) {
             const Compact<T> m0 = compact_moments(K, ginv, u0, u1, u2, fB0, fB1, fB2);
             if (newcell) {
-              if (ca.cell >= 0) ca.flush(acc, plane, LW, lz, dens, oD0, oD1, oD2);
+              if (ca.cell >= 0) ca.flush(acc, lz, dplane);
               ca.clear();
               ca.cell = li;
             }
@@ -879,7 +873,7 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
                 fz2 = zn - (double)k2;
               }
               if (newcell) {
-                if (ca.cell >= 0) ca.flush(acc, plane, LW, lz, dens, oD0, oD1, oD2);
+                if (ca.cell >= 0) ca.flush(acc, lz, dplane);
                 ca.clear();
                 ca.cell = li;
               }
@@ -917,7 +911,7 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
             const int nm = __popcll(mmask);
             if (nq + nm > kMqCap) {
               wave_sync();
-              drain_movers(mq, nq, lane, acc, plane, LW, dens, K.w, Hn, Lo.NPL);
+              drain_movers(mq, nq, lane, acc, dplane, K.w);
               wave_sync();
               nq = 0;
             }
@@ -938,10 +932,10 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
           }
         }
       }
-      ca.flush_row_end(acc, plane, LW, lz, dens, fD0, fD1, fD2, lane);
+      ca.flush_row_end(acc, lz, dplane, lane);
       if (PUSH && nq > 0) {
         wave_sync();
-        drain_movers(mq, nq, lane, acc, plane, LW, dens, K.w, Hn, Lo.NPL);
+        drain_movers(mq, nq, lane, acc, dplane, K.w);
         wave_sync();
       }
     }
@@ -987,9 +981,12 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
     gz = wrap_any(gz, g.nz);
     if (in) a.mtile[(gz / t.tz) * t.ntx + min(gx, g.nx - 1) / t.tx] = 1;
   }
-  // fold the tile's accumulators into the global FP64 moment planes
-  for (int e = threadIdx.x; e < g.n_planes * plane; e += blockDim.x) {
-    const double v = acc[e];
+  // Fold the tile's accumulators into the global FP64 moment planes: delta-j and density as
+  // they are; S-hat at a node from the S-hat scalars of the (up to) four cells around it, each
+  // expanded with its cell's B (H^{n+3/2} after a push, H^{n+1/2} for a deposit of the current
+  // state): S-hat = a0 I + a1 [B]x + a2 B B^T.
+  for (int e = threadIdx.x; e < Lo.n_node * plane; e += blockDim.x) {
+    const double v = acc.node[e];
     if (v == 0.0) continue;
     const int pp = e / plane, idx = e - pp * plane;
     const int lzz = idx / LW, lx = idx - lzz * LW;
@@ -1000,7 +997,57 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
       continue;
     }
     gz = wrap_any(gz, g.nz);
-    unsafeAtomicAdd(&a.M[(int64_t)pp * nn + (int64_t)gz * g.nxn + gx], v);
+    const int gp = pp < 3 ? 9 + pp : 12 + (pp - 3);
+    unsafeAtomicAdd(&a.M[(int64_t)gp * nn + (int64_t)gz * g.nxn + gx], v);
+  }
+  const int NH = t.tz + 2;
+  for (int e = threadIdx.x; e < plane; e += blockDim.x) {
+    const int lzz = e / LW, lx = e - lzz * LW;
+    double S[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    bool any = false;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int rx = lx - (c & 1), rz = lzz - (c >> 1);  // the cell whose corner c is this node
+      if (rx < 0 || rx >= Lo.NW || rz < 0 || rz >= NH) continue;
+      const int rc = rz * Lo.NW + rx;
+      const double A0 = acc.cell[(0 * 4 + c) * Lo.NPL + rc];
+      const double A1 = acc.cell[(1 * 4 + c) * Lo.NPL + rc];
+      const double A2 = acc.cell[(2 * 4 + c) * Lo.NPL + rc];
+      if (A0 == 0.0 && A1 == 0.0 && A2 == 0.0) continue;
+      double B0 = 0.0, B1 = 0.0, B2 = 0.0;
+      if (PUSH) {
+        B0 = (double)Hn[rc];
+        B1 = (double)Hn[Lo.NPL + rc];
+        B2 = (double)Hn[2 * Lo.NPL + rc];
+      } else if (rx >= 1 && rx <= t.tx && rz >= 1 && rz <= t.tz) {
+        const int hc = (rz - 1) * t.tx + (rx - 1);
+        B0 = (double)Ho[hc];
+        B1 = (double)Ho[Lo.HPL + hc];
+        B2 = (double)Ho[2 * Lo.HPL + hc];
+      }
+      S[0] += fma(A2, B0 * B0, A0);
+      S[1] += fma(A2, B0 * B1, A1 * B2);
+      S[2] += fma(A2, B0 * B2, -A1 * B1);
+      S[3] += fma(A2, B1 * B0, -A1 * B2);
+      S[4] += fma(A2, B1 * B1, A0);
+      S[5] += fma(A2, B1 * B2, A1 * B0);
+      S[6] += fma(A2, B2 * B0, A1 * B1);
+      S[7] += fma(A2, B2 * B1, -A1 * B0);
+      S[8] += fma(A2, B2 * B2, A0);
+      any = true;
+    }
+    if (!any) continue;
+    int gx = i0 - 1 + lx, gz = k0 - 1 + lzz;
+    if (g.bc_x == PIC_BC_PERIODIC) {
+      gx = wrap_any(gx, g.nx);
+    } else if (gx < 0 || gx > g.nx) {
+      continue;
+    }
+    gz = wrap_any(gz, g.nz);
+    const int64_t node = (int64_t)gz * g.nxn + gx;
+#pragma unroll
+    for (int r = 0; r < 9; ++r)
+      if (S[r] != 0.0) unsafeAtomicAdd(&a.M[(int64_t)r * nn + node], S[r]);
   }
 }
 

@@ -260,7 +260,7 @@ def test_argument_errors(pic):
         ctx.load_particles(1, -1.0, 1.0, 1.0, [1.0], [0.5], [0.0], [0.0], [0.0])
     assert e.value.status == 1
     ctx.close()
-    big = pic.Context(g, tile=(64, 64))   # LDS accumulators of such a tile exceed 64 KiB
+    big = pic.Context(g, tile=(64, 64))   # LDS accumulators of such a tile exceed a block's LDS
     with pytest.raises(pic.PicError) as e:
         big.load_particles(0, -1.0, 1.0, 1.0, [1.0], [0.5], [0.0], [0.0], [0.0])
     assert e.value.status == 1 and "tile too large" in str(e.value)
