@@ -13,6 +13,8 @@ LIB = os.path.join(HERE, "liborc.so")
 
 PERIODIC = 0
 ABSORBING = 1
+GAMMA_PREDICT = 1   # mover option: gamma-bar = gamma(u^n + beta E^n) (reading R1's alternative)
+B_BILINEAR = 2      # mover option: B interpolated from the four cell centres (R5's alternative)
 
 
 def build(force: bool = True) -> str:
@@ -52,12 +54,14 @@ def load_library():
         lib.orc_nodes_x.restype = C.c_int32
         lib.orc_nodes_z.restype = C.c_int32
         lib.orc_response.argtypes = [C.c_double, C.c_double, C.c_double, P, P, P, P]
-        lib.orc_deposit.argtypes = [P, C.c_int32, P, P, P]
+        lib.orc_response_g.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, P, P]
+        lib.orc_deposit.argtypes = [P, C.c_int32, P, P, P, C.c_int32, P]
         lib.orc_gather.argtypes = [P, P, C.c_int32, C.c_int64, P, P, P]
+        lib.orc_particle_B.argtypes = [P, P, C.c_int32, C.c_int64, P, P, P]
         lib.orc_incident_ey.argtypes = [P, C.c_double, C.c_double, C.c_double]
         lib.orc_incident_ey.restype = C.c_double
         lib.orc_field_solve.argtypes = [P, C.c_double, P, P, P, P, P, P]
-        lib.orc_push.argtypes = [P, P, P, P, P]
+        lib.orc_push.argtypes = [P, P, P, P, P, C.c_int32, P]
         lib.orc_sort.argtypes = [P, P, P, P]
         lib.orc_sort.restype = C.c_int64
         _lib = lib
@@ -101,10 +105,12 @@ class OracleSim:
     """One simulation held in numpy arrays, advanced by the C oracle.
 
     State after k cycles: positions x^{k+1/2} (cell units), momenta u^k, E^k on nodes,
-    H^{k+1/2} at cell centres and t = k dt.
+    H^{k+1/2} at cell centres and t = k dt.  mode selects the mover options (GAMMA_PREDICT,
+    B_BILINEAR; 0 = the defaults).
     """
 
-    def __init__(self, grid):
+    def __init__(self, grid, mode=0):
+        self.mode = int(mode)
         self.lib = load_library()
         self.g = make_grid(grid)
         if self.g.bc_z != PERIODIC:
@@ -141,15 +147,17 @@ class OracleSim:
         self.H = np.ascontiguousarray(np.array(H, dtype=np.float64).reshape(3, self.g.nz, self.g.nx))
 
     # -- the pieces of one cycle ----------------------------------------------------------
-    def moments(self, H=None):
+    def moments(self, H=None, E=None):
         """M^{k+1/2}: S-hat (9), delta-j (3) and S densities on the nodes."""
         H = self.H if H is None else H
+        E = self.E if E is None else E
         M = np.zeros((12 + self.S, self.nzn, self.nxn))
         for s, sp in enumerate(self.species):
             if sp is None or sp.n == 0:
                 continue
             st = sp.struct()
-            self.lib.orc_deposit(C.byref(self.g), s, C.byref(st), _ptr(np.ascontiguousarray(H)), _ptr(M))
+            self.lib.orc_deposit(C.byref(self.g), s, C.byref(st), _ptr(np.ascontiguousarray(H)),
+                                 _ptr(np.ascontiguousarray(E)), self.mode, _ptr(M))
         return M
 
     def field_solve(self, M):
@@ -160,12 +168,14 @@ class OracleSim:
                                  _ptr(E_new), _ptr(Ebar), _ptr(H_new))
         return E_new, Ebar, H_new
 
-    def push(self, s, Ebar, H):
+    def push(self, s, Ebar, H, E=None):
         sp = self.species[s]
+        E = self.E if E is None else E
         alive = np.ones(sp.n, dtype=np.uint8)
         st = sp.struct()
         self.lib.orc_push(C.byref(self.g), C.byref(st), _ptr(np.ascontiguousarray(Ebar)),
-                          _ptr(np.ascontiguousarray(H)), _ptr(alive))
+                          _ptr(np.ascontiguousarray(H)), _ptr(np.ascontiguousarray(E)), self.mode,
+                          _ptr(alive))
         return alive
 
     def sort(self, s, alive=None):
@@ -206,8 +216,41 @@ class OracleSim:
                             _ptr(np.ascontiguousarray(xi_z, dtype=np.float64)), _ptr(out))
         return out
 
+    def particle_B(self, H, xi_x, xi_z, mode=None):
+        """B at the given positions as the mover sees it (this simulation's mode by default)."""
+        H = np.ascontiguousarray(H, dtype=np.float64)
+        n = len(xi_x)
+        out = np.zeros((3, n))
+        self.lib.orc_particle_B(C.byref(self.g), _ptr(H), self.mode if mode is None else int(mode),
+                                n, _ptr(np.ascontiguousarray(xi_x, dtype=np.float64)),
+                                _ptr(np.ascontiguousarray(xi_z, dtype=np.float64)), _ptr(out))
+        return out
+
+    def energy(self):
+        """Energies of the current state (the plain definitions): [field, kinetic of species
+        0, 1, ...] with field = (1/2)(sum over nodes of |E^k|^2 + sum over cells of
+        |H^{k+1/2}|^2) dx dz and kinetic = sum over particles of w m (gamma(u^k) - 1) dx dz."""
+        area = float(self.g.dx) * float(self.g.dz)
+        out = [0.5 * (float(np.sum(self.E * self.E)) + float(np.sum(self.H * self.H))) * area]
+        for sp in self.species:
+            if sp is None or sp.n == 0:
+                out.append(0.0)
+                continue
+            gam = np.sqrt(1.0 + sp.ux * sp.ux + sp.uy * sp.uy + sp.uz * sp.uz)
+            out.append(float(np.sum(sp.w * sp.m * (gam - 1.0))) * area)
+        return out
+
     def incident_ey(self, t, x, z):
         return self.lib.orc_incident_ey(C.byref(self.g), float(t), float(x), float(z))
+
+
+def response_g(q, m, dt, gamma, B):
+    """R of one particle for a given gamma-bar (exposed for the tests)."""
+    lib = load_library()
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    R = np.zeros(9)
+    lib.orc_response_g(float(q), float(m), float(dt), float(gamma), _ptr(B), _ptr(R))
+    return R.reshape(3, 3)
 
 
 def response(q, m, dt, u, B):

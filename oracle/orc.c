@@ -39,10 +39,8 @@ static int32_t wrap_cell(int32_t i, int32_t ncell) {
   return i;
 }
 
-/* Eq. (2a) solved for the time-centred momentum: the 3x3 matrix R and gamma-bar = gamma(u^n). */
-void orc_response(double q, double m, double dt, const double u[3], const double B[3],
-                  double R[9], double *gamma) {
-  double g = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+/* Eq. (2a) solved for the time-centred momentum: the 3x3 matrix R for a given gamma-bar. */
+void orc_response_g(double q, double m, double dt, double g, const double B[3], double R[9]) {
   double beta = q * dt / (2.0 * m);
   double bg = beta / g;
   double bx = bg * B[0], by = bg * B[1], bz = bg * B[2];
@@ -56,6 +54,13 @@ void orc_response(double q, double m, double dt, const double u[3], const double
   R[6] = (by + bz * bx) * inv;
   R[7] = (-bx + bz * by) * inv;
   R[8] = (1.0 + bz * bz) * inv;
+}
+
+/* The same with gamma-bar = gamma(u^n), the lagged Lorentz factor. */
+void orc_response(double q, double m, double dt, const double u[3], const double B[3],
+                  double R[9], double *gamma) {
+  double g = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  orc_response_g(q, m, dt, g, B, R);
   *gamma = g;
 }
 
@@ -83,21 +88,84 @@ static void cell_weights(const orc_grid *g, double xi_x, double xi_z, int32_t no
   *cell_k = k;
 }
 
-/* Sec. 3.3 Step 1 with Eq. (3): S-hat and delta-j accumulated on the nodes from the particles
- * at x^{n+1/2} with u^n and B = H^{n+1/2} of the particle's cell; plus the species density. */
-void orc_deposit(const orc_grid *g, int32_t s, const orc_species *sp, const double *H, double *M) {
-  int64_t nnodes = (int64_t)orc_nodes_x(g) * orc_nodes_z(g);
+/* B at the particle from the cell-centred H (R5).  Default: H of the particle's own cell.
+ * ORC_B_BILINEAR: bilinear interpolation between the four cell centres around the particle
+ * (centres at i + 1/2, k + 1/2); periodic axes wrap; on an absorbing x axis a centre index
+ * beyond the edge is clamped to the edge cell. */
+static void particle_B(const orc_grid *g, const double *H, double xi_x, double xi_z, int32_t mode,
+                       double B[3]) {
   int64_t ncells = (int64_t)g->nx * g->nz;
+  if (!(mode & ORC_B_BILINEAR)) {
+    int64_t c = (int64_t)floor(xi_z) * g->nx + (int64_t)floor(xi_x);
+    for (int r = 0; r < 3; ++r) B[r] = H[r * ncells + c];
+    return;
+  }
+  double sx = xi_x - 0.5, sz = xi_z - 0.5;
+  int32_t ic = (int32_t)floor(sx), kc = (int32_t)floor(sz);
+  double gx = sx - (double)ic, gz = sz - (double)kc;
+  int32_t ci[2], ck[2];
+  for (int t = 0; t < 2; ++t) {
+    int32_t i = ic + t, k = kc + t;
+    if (g->bc_x == ORC_PERIODIC) {
+      ci[t] = wrap_cell(i, g->nx);
+    } else {
+      ci[t] = i < 0 ? 0 : (i >= g->nx ? g->nx - 1 : i);
+    }
+    ck[t] = wrap_cell(k, g->nz);
+  }
+  double Wc[4] = {(1.0 - gx) * (1.0 - gz), gx * (1.0 - gz), (1.0 - gx) * gz, gx * gz};
+  int64_t c4[4] = {(int64_t)ck[0] * g->nx + ci[0], (int64_t)ck[0] * g->nx + ci[1],
+                   (int64_t)ck[1] * g->nx + ci[0], (int64_t)ck[1] * g->nx + ci[1]};
+  for (int r = 0; r < 3; ++r)
+    B[r] = Wc[0] * H[r * ncells + c4[0]] + Wc[1] * H[r * ncells + c4[1]] +
+           Wc[2] * H[r * ncells + c4[2]] + Wc[3] * H[r * ncells + c4[3]];
+}
+
+void orc_particle_B(const orc_grid *g, const double *H, int32_t mode, int64_t n,
+                    const double *xi_x, const double *xi_z, double *out) {
+  for (int64_t a = 0; a < n; ++a) {
+    double B[3];
+    particle_B(g, H, xi_x[a], xi_z[a], mode, B);
+    for (int r = 0; r < 3; ++r) out[r * n + a] = B[r];
+  }
+}
+
+/* gamma-bar of the linearised mover (R1).  Default: gamma(u^n).  ORC_GAMMA_PREDICT: the
+ * Boris-style predictor gamma(u^n + beta E^n), E^n (the field before the solve) interpolated
+ * linearly at the particle; the deposit and the push of a cycle use the same value. */
+static double particle_gamma(const orc_grid *g, const double *E, double q, double m,
+                             const double u[3], const int32_t node[4], const double W[4],
+                             int32_t mode) {
+  if (!(mode & ORC_GAMMA_PREDICT))
+    return sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  int64_t nnodes = (int64_t)orc_nodes_x(g) * orc_nodes_z(g);
+  double beta = q * g->dt / (2.0 * m);
+  double um[3];
+  for (int r = 0; r < 3; ++r) {
+    const double *f = E + r * nnodes;
+    double e = W[0] * f[node[0]] + W[1] * f[node[1]] + W[2] * f[node[2]] + W[3] * f[node[3]];
+    um[r] = u[r] + beta * e;
+  }
+  return sqrt(1.0 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+}
+
+/* Sec. 3.3 Step 1 with Eq. (3): S-hat and delta-j accumulated on the nodes from the particles
+ * at x^{n+1/2} with u^n and B = H^{n+1/2} at the particle; plus the species density.  E is E^n
+ * (read by ORC_GAMMA_PREDICT only; may be NULL otherwise). */
+void orc_deposit(const orc_grid *g, int32_t s, const orc_species *sp, const double *H,
+                 const double *E, int32_t mode, double *M) {
+  int64_t nnodes = (int64_t)orc_nodes_x(g) * orc_nodes_z(g);
   double cS = sp->q * sp->q * g->dt * g->dt / (4.0 * sp->m);
   for (int64_t a = 0; a < sp->n; ++a) {
     int32_t node[4], ci, ck;
     double W[4];
     cell_weights(g, sp->xi_x[a], sp->xi_z[a], node, W, &ci, &ck);
-    int64_t c = (int64_t)ck * g->nx + ci;
-    double B[3] = {H[c], H[ncells + c], H[2 * ncells + c]};
+    double B[3];
+    particle_B(g, H, sp->xi_x[a], sp->xi_z[a], mode, B);
     double u[3] = {sp->ux[a], sp->uy[a], sp->uz[a]};
-    double R[9], gam;
-    orc_response(sp->q, sp->m, g->dt, u, B, R, &gam);
+    double R[9];
+    double gam = particle_gamma(g, E, sp->q, sp->m, u, node, W, mode);
+    orc_response_g(sp->q, sp->m, g->dt, gam, B, R);
     double w = sp->w[a];
     double kS = w * cS / gam;
     double kJ = w * sp->q / gam;
@@ -245,26 +313,28 @@ void orc_field_solve(const orc_grid *g, double t, const double *M, const double 
 
 /*
  * The implicit mover (Sec. 2, Eq. (2); pushed once per cycle, Sec. 1): with E-bar gathered at
- * x^{n+1/2} and B = H^{n+1/2} of the particle's cell, u-bar = R (u^n + beta E-bar),
- * u^{n+1} = 2 u-bar - u^n, then x^{n+3/2} = x^{n+1/2} + dt u^{n+1} / gamma(u^{n+1}) (Eqs. 2b-2c).
+ * x^{n+1/2} and B = H^{n+1/2} at the particle (its cell's, or bilinear with ORC_B_BILINEAR),
+ * u-bar = R (u^n + beta E-bar), u^{n+1} = 2 u-bar - u^n, then
+ * x^{n+3/2} = x^{n+1/2} + dt u^{n+1} / gamma(u^{n+1}) (Eqs. 2b-2c).  E is E^n, read for the
+ * gamma-bar predictor only (ORC_GAMMA_PREDICT; may be NULL otherwise).
  * Periodic axes wrap; a particle leaving an absorbing x axis is removed (it leaves the domain,
  * as particles leaving a processor's strip leave that processor, Sec. 3.3).
  */
 void orc_push(const orc_grid *g, orc_species *sp, const double *Ebar, const double *H,
-              uint8_t *alive) {
+              const double *E, int32_t mode, uint8_t *alive) {
   int64_t nnodes = (int64_t)orc_nodes_x(g) * orc_nodes_z(g);
-  int64_t ncells = (int64_t)g->nx * g->nz;
   double beta = sp->q * g->dt / (2.0 * sp->m);
   double cx = g->dt / g->dx, cz = g->dt / g->dz;
   for (int64_t a = 0; a < sp->n; ++a) {
     int32_t node[4], ci, ck;
     double W[4];
     cell_weights(g, sp->xi_x[a], sp->xi_z[a], node, W, &ci, &ck);
-    int64_t c = (int64_t)ck * g->nx + ci;
-    double B[3] = {H[c], H[ncells + c], H[2 * ncells + c]};
+    double B[3];
+    particle_B(g, H, sp->xi_x[a], sp->xi_z[a], mode, B);
     double u[3] = {sp->ux[a], sp->uy[a], sp->uz[a]};
-    double R[9], gam;
-    orc_response(sp->q, sp->m, g->dt, u, B, R, &gam);
+    double R[9];
+    double gam = particle_gamma(g, E, sp->q, sp->m, u, node, W, mode);
+    orc_response_g(sp->q, sp->m, g->dt, gam, B, R);
     double Ep[3];
     for (int r = 0; r < 3; ++r) {
       const double *f = Ebar + r * nnodes;

@@ -35,6 +35,12 @@ extern "C" {
 
 enum { ORC_PERIODIC = 0, ORC_ABSORBING = 1 };
 
+/* Mover options (readings R1 and R5 of the paper; 0 is the default of both):
+ *   ORC_GAMMA_PREDICT  gamma-bar = gamma(u^n + beta E^n) instead of gamma(u^n);
+ *   ORC_B_BILINEAR     B at the particle interpolated from the four surrounding cell centres
+ *                      instead of the particle's own cell. */
+enum { ORC_GAMMA_PREDICT = 1, ORC_B_BILINEAR = 2 };
+
 typedef struct {
   int32_t nx, nz;          /* cells along x and z */
   double dx, dz, dt;
@@ -55,16 +61,25 @@ typedef struct {
 int32_t orc_nodes_x(const orc_grid *g);
 int32_t orc_nodes_z(const orc_grid *g);
 
-/* Implicit response of one particle: R = (I + [b]x + b b^T) / (1 + b.b), b = beta B / gamma. */
+/* Implicit response of one particle: R = (I + [b]x + b b^T) / (1 + b.b), b = beta B / gamma,
+ * for a given gamma-bar (orc_response_g) or gamma-bar = gamma(u) (orc_response). */
+void orc_response_g(double q, double m, double dt, double gamma, const double B[3], double R[9]);
 void orc_response(double q, double m, double dt, const double u[3], const double B[3],
                   double R[9], double *gamma);
 
-/* Add species s's implicit source moments S-hat, delta-j and density to M (Sec. 3.3 Step 1). */
-void orc_deposit(const orc_grid *g, int32_t s, const orc_species *sp, const double *H, double *M);
+/* Add species s's implicit source moments S-hat, delta-j and density to M (Sec. 3.3 Step 1).
+ * E = E^n (read with ORC_GAMMA_PREDICT only); mode = ORC_* mover options. */
+void orc_deposit(const orc_grid *g, int32_t s, const orc_species *sp, const double *H,
+                 const double *E, int32_t mode, double *M);
 
 /* Linear (bilinear) interpolation of ncomp node planes to n particle positions. */
 void orc_gather(const orc_grid *g, const double *F, int32_t ncomp, int64_t n,
                 const double *xi_x, const double *xi_z, double *out);
+
+/* B at n particle positions as the mover sees it (mode & ORC_B_BILINEAR selects the
+ * interpolation), out[3][n]. */
+void orc_particle_B(const orc_grid *g, const double *H, int32_t mode, int64_t n,
+                    const double *xi_x, const double *xi_z, double *out);
 
 /* Incident laser E_y at time t and point (x, z) (the source added at x = 0, Step 4). */
 double orc_incident_ey(const orc_grid *g, double t, double x, double z);
@@ -73,9 +88,10 @@ double orc_incident_ey(const orc_grid *g, double t, double x, double z);
 void orc_field_solve(const orc_grid *g, double t, const double *M, const double *E,
                      const double *H, double *E_new, double *Ebar, double *H_new);
 
-/* Implicit push of one species in E-bar and H^{n+1/2}; alive[p] = 0 if absorbed. */
+/* Implicit push of one species in E-bar and H^{n+1/2}; alive[p] = 0 if absorbed.  E = E^n
+ * (read with ORC_GAMMA_PREDICT only); mode = ORC_* mover options. */
 void orc_push(const orc_grid *g, orc_species *sp, const double *Ebar, const double *H,
-              uint8_t *alive);
+              const double *E, int32_t mode, uint8_t *alive);
 
 /* Stable counting sort of alive particles by cell key k*nx + i; returns the new count.
  * perm_out (may be NULL) receives, for each new position, the old index. */

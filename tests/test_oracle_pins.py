@@ -392,3 +392,188 @@ def test_absorbing_removal_and_periodic_wrap_edges():
     assert sim.absorbed[0] == 2 and len(p["id"]) == 3
     assert np.all((p["xi_z"] >= 0.0) & (p["xi_z"] < g.nz))
     assert np.all((p["xi_x"] >= 0.0) & (p["xi_x"] < g.nx))
+
+
+# --- mover options (alternative readings of the Lorentz factor and of B at the particle) ---------
+
+from oracle.oracle import B_BILINEAR, GAMMA_PREDICT  # noqa: E402
+
+
+def _textbook_boris(u, E, B, q, m, dt):
+    """Relativistic Boris step: half electric kick, rotation with gamma of the kicked momentum,
+    half electric kick."""
+    beta = q * dt / (2.0 * m)
+    um = u + beta * E
+    g = math.sqrt(1.0 + float(um @ um))
+    t = beta * B / g
+    s = 2.0 * t / (1.0 + float(t @ t))
+    up = um + np.cross(um, t)
+    return um + np.cross(up, s) + beta * E
+
+
+@pytest.mark.parametrize("q,m", [(-1.0, 1.0), (1.0, 7.0)])
+def test_gamma_predictor_is_relativistic_boris(q, m):
+    """In uniform fields, the mover with gamma-bar = gamma(u^n + beta E^n) is the relativistic
+    Boris step (Cayley rotation of the half-kicked momentum)."""
+    rng = np.random.default_rng(11)
+    g = _grid(nx=4, nz=4, dx=1.0, dz=1.0, dt=0.4)
+    for trial in range(5):
+        E = rng.normal(0, 0.7, 3)
+        B = rng.normal(0, 1.5, 3)
+        sim = OracleSim(g, mode=GAMMA_PREDICT)
+        En = np.zeros((3, sim.nzn, sim.nxn))
+        H = np.zeros((3, g.nz, g.nx))
+        for r in range(3):
+            En[r] = E[r]
+            H[r] = B[r]
+        sim.load_fields(En, H)
+        u = rng.normal(0, 2.0, (3, 3))
+        _load(sim, 0, q, m, 1.0, [0.3, 1.7, 2.2], [0.6, 3.1, 1.4], u)
+        p0 = sim.particles(0)
+        sim.push(0, En, H)   # E-bar = E^n = E: uniform, constant field
+        p1 = sim.particles(0)
+        for a in range(3):
+            u0 = np.array([p0["ux"][a], p0["uy"][a], p0["uz"][a]])
+            u1 = np.array([p1["ux"][a], p1["uy"][a], p1["uz"][a]])
+            ref = _textbook_boris(u0, E, B, q, m, g.dt)
+            assert np.max(np.abs(u1 - ref)) <= 1e-13 * (1.0 + np.max(np.abs(ref)))
+
+
+def test_mover_options_coincide_where_they_should():
+    """With E^n = 0 the Lorentz-factor predictor equals the lagged factor exactly; with uniform H
+    the bilinear B equals the cell's B to rounding."""
+    rng = np.random.default_rng(4)
+    g = _grid(nx=5, nz=4, dx=0.8, dz=0.6, dt=0.35)
+    B = np.array([0.4, -0.9, 1.2])
+    H = np.zeros((3, g.nz, g.nx))
+    for r in range(3):
+        H[r] = B[r]
+    n = 40
+    xi_x, xi_z = rng.uniform(0, g.nx, n), rng.uniform(0, g.nz, n)
+    u = rng.normal(0, 1.0, (n, 3))
+    res = {}
+    for mode in (0, GAMMA_PREDICT, B_BILINEAR):
+        sim = OracleSim(g, mode=mode)
+        sim.load_fields(sim.E, H)
+        _load(sim, 0, -1.0, 1.0, 1.0, xi_x, xi_z, u)
+        Eb = np.full((3, sim.nzn, sim.nxn), 0.05)
+        M = sim.moments()
+        sim.push(0, Eb, H)
+        p = sim.particles(0)
+        res[mode] = (M, np.stack([p["ux"], p["uy"], p["uz"]]))
+    assert np.array_equal(res[0][0], res[GAMMA_PREDICT][0])
+    assert np.array_equal(res[0][1], res[GAMMA_PREDICT][1])
+    assert np.max(np.abs(res[0][0] - res[B_BILINEAR][0])) <= 1e-14 * np.max(np.abs(res[0][0]))
+    assert np.max(np.abs(res[0][1] - res[B_BILINEAR][1])) <= 1e-14 * np.max(np.abs(res[0][1]))
+
+
+@pytest.mark.parametrize("bc_x", [0, 1])
+def test_bilinear_B_matches_library_interpolation(bc_x):
+    """Bilinear B from the cell centres equals scipy's linear grid interpolation on the centres
+    (the grid padded by one cell: wrapped on periodic axes, the edge cell repeated on an
+    absorbing x axis), and reproduces a field linear in x and z exactly away from the wrap."""
+    from scipy.interpolate import RegularGridInterpolator
+    rng = np.random.default_rng(8 + bc_x)
+    g = _grid(nx=7, nz=5, dx=0.6, dz=0.9, dt=0.3, bc_x=bc_x)
+    sim = OracleSim(g, mode=B_BILINEAR)
+    H = rng.normal(size=(3, g.nz, g.nx))
+    n = 200
+    xi_x, xi_z = rng.uniform(0, g.nx, n), rng.uniform(0, g.nz, n)
+    got = sim.particle_B(H, xi_x, xi_z)
+    xc = np.arange(-1, g.nx + 1) + 0.5
+    zc = np.arange(-1, g.nz + 1) + 0.5
+    for r in range(3):
+        P = np.pad(H[r], 1, mode="wrap")
+        if bc_x == 1:
+            P[:, 0] = P[:, 1]
+            P[:, -1] = P[:, -2]
+        f = RegularGridInterpolator((zc, xc), P, method="linear")
+        ref = f(np.stack([xi_z, xi_x], 1))
+        assert np.max(np.abs(got[r] - ref)) <= 1e-13
+    # a linear field (no wrap inside [1, nx-1] x [1, nz-1])
+    zz, xx = np.meshgrid(np.arange(g.nz) + 0.5, np.arange(g.nx) + 0.5, indexing="ij")
+    Hl = np.stack([0.3 + 0.7 * xx - 0.2 * zz, -1.0 + 0.1 * xx, 2.0 - 0.5 * zz])
+    px, pz = rng.uniform(1.0, g.nx - 1.0, n), rng.uniform(1.0, g.nz - 1.0, n)
+    got = sim.particle_B(Hl, px, pz)
+    ref = np.stack([0.3 + 0.7 * px - 0.2 * pz, -1.0 + 0.1 * px, 2.0 - 0.5 * pz])
+    assert np.max(np.abs(got - ref)) <= 1e-13
+    # the default reads the particle's own cell
+    own = sim.particle_B(H, px, pz, mode=0)
+    ci, ck = np.floor(px).astype(int), np.floor(pz).astype(int)
+    assert np.array_equal(own, H[:, ck, ci])
+
+
+@pytest.mark.parametrize("mode", [0, GAMMA_PREDICT, B_BILINEAR, GAMMA_PREDICT | B_BILINEAR])
+def test_current_consistency_every_mover_option(mode):
+    """In every mover option the deposited S-hat and delta-j split the current of the mover's own
+    u-bar / gamma-bar (uniform E-bar; non-uniform H and E^n, so B and gamma-bar vary per particle)."""
+    rng = np.random.default_rng(21 + mode)
+    g = _grid(nx=5, nz=4, dx=0.9, dz=0.6, dt=0.45, n_species=1)
+    sim = OracleSim(g, mode=mode)
+    H = rng.normal(0, 0.8, (3, g.nz, g.nx))
+    En = rng.normal(0, 0.5, (3, sim.nzn, sim.nxn))
+    sim.load_fields(En, H)
+    n = 60
+    xi_x, xi_z = rng.uniform(0, g.nx, n), rng.uniform(0, g.nz, n)
+    u = rng.normal(0, 1.2, (n, 3))
+    q, m, w = -1.0, 1.0, 0.8
+    _load(sim, 0, q, m, w, xi_x, xi_z, u)
+    M = sim.moments()
+    p0 = sim.particles(0)
+    Eb = np.array([0.2, -0.05, 0.13])
+    Ebar = np.zeros((3, sim.nzn, sim.nxn))
+    for r in range(3):
+        Ebar[r] = Eb[r]
+    sim.push(0, Ebar, H)
+    p1 = sim.particles(0)
+    u0 = np.stack([p0["ux"], p0["uy"], p0["uz"]], 1)
+    u1 = np.stack([p1["ux"], p1["uy"], p1["uz"]], 1)
+    if mode & GAMMA_PREDICT:
+        beta = q * g.dt / (2.0 * m)
+        Wt = pc.tent_weights(g.nx, g.nz, 0, p0["xi_x"], p0["xi_z"])
+        Ep = np.einsum("pki,cki->pc", Wt, En)
+        um = u0 + beta * Ep
+        gam = np.sqrt(1.0 + np.sum(um * um, 1))
+    else:
+        gam = np.sqrt(1.0 + np.sum(u0 * u0, 1))
+    jp = w * q * 0.5 * (u0 + u1) / gam[:, None]
+    Wt = pc.tent_weights(g.nx, g.nz, 0, p0["xi_x"], p0["xi_z"])
+    J = np.einsum("pki,pc->cki", Wt, jp)
+    S = M[:9].reshape(3, 3, g.nz, g.nx)
+    pred = (2.0 / g.dt) * np.einsum("rcki,c->rki", S, Eb) + M[9:12]
+    assert np.max(np.abs(J - pred)) <= 1e-13 * np.max(np.abs(J))
+
+
+def test_energy_definitions_and_cold_plasma_conservation():
+    """Field energy (1/2)(sum |E|^2 over nodes + sum |H|^2 over cells) dx dz and kinetic energy
+    sum w m (gamma - 1) dx dz: closed forms for uniform fields and one particle; the total is
+    conserved by the implicit-midpoint cycle of a cold uniform plasma (dx dz != 1, so a factor
+    missing from one term would show)."""
+    g = _grid(nx=4, nz=3, dx=0.8, dz=0.6, dt=0.5, n_species=1, e0=(0.3, -0.2, 0.1),
+              h0=(0.0, 0.4, -0.5))
+    sim = OracleSim(g)
+    _load(sim, 0, -1.0, 3.0, 0.7, [1.2], [2.5], [[0.5, -1.0, 2.0]])
+    W = sim.energy()
+    area = 0.8 * 0.6
+    assert math.isclose(W[0], 0.5 * (0.14 * 12 + 0.41 * 12) * area, rel_tol=1e-14)
+    assert math.isclose(W[1], 0.7 * 3.0 * (math.sqrt(1.0 + 5.25) - 1.0) * area, rel_tol=1e-14)
+    # a plasma oscillation from moving particles and no field: about a fifth of the energy
+    # passes into E and back
+    rng = np.random.default_rng(6)
+    amp = 1e-4
+    g = _grid(nx=4, nz=4, dx=0.8, dz=0.6, dt=0.5, n_species=2)
+    sim = OracleSim(g)
+    for s, (q, m) in enumerate([(-1.0, 1.0), (1.0, 25.0)]):
+        sp = picgen.make_species(np.random.default_rng(0), *np.meshgrid(np.arange(4), np.arange(4)),
+                                 4, q=q, m=m, density=1.0, temperature_kev=0.0, quiet=True)
+        u = amp * rng.normal(size=3)
+        sim.load_species(s, q, m, sp.w, sp.xi_x, sp.xi_z, np.full(sp.n, u[0]),
+                         np.full(sp.n, u[1]), np.full(sp.n, u[2]))
+    W0 = sum(sim.energy())
+    field_share = 0.0
+    for _ in range(20):
+        sim.step(1)
+        W = sim.energy()
+        field_share = max(field_share, W[0] / W0)
+        assert abs(sum(W) - W0) <= 1e-6 * W0   # gamma - 1 = u^2/2 + O(u^4): about 2e-8 here
+    assert field_share > 0.1
