@@ -90,6 +90,9 @@ def parse():
                     help="timed cycles of each FP64 / mixed comparison run (0 skips them)")
     ap.add_argument("--drift-steps", type=int, default=500,
                     help="cycles of the FP64 / mixed drift comparison on the dense foil (0 skips it)")
+    ap.add_argument("--mover-steps", type=int, default=1000,
+                    help="cycles of the warm-plasma energy comparison of the mover options "
+                         "(0 skips the mover-option section)")
     ap.add_argument("--serve-runs", type=int, default=256,
                     help="requests of the batched serving stream (0 skips it)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="request arrivals per second")
@@ -247,6 +250,72 @@ def drift(binding, steps, name="foil_dense"):
             "mixed_vs_fp64_rounded_inputs": errs(runs["mixed"], runs["fp64_rounded_inputs"])}
 
 
+def warm_plasma(temperature_kev, nx=128, nz=128, ppc=16):
+    """Periodic two-species plasma with thermal electrons at temperature_kev (cold ions, m_i/m_e
+    = 1836), density 1, dx = dz = 1.25, dt = 0.5 (omega_p dt = 0.5), uniform B_z = 0.5, E = 0."""
+    import numpy as np
+    ci, ck = np.meshgrid(np.arange(nx), np.arange(nz))
+    el = picgen.make_species(np.random.default_rng(71), ci.ravel(), ck.ravel(), ppc, q=-1.0,
+                             m=1.0, density=1.0, temperature_kev=temperature_kev, quiet=False)
+    io = picgen.make_species(np.random.default_rng(72), ci.ravel(), ck.ravel(), ppc, q=1.0,
+                             m=picgen.ION_MASS, density=1.0, temperature_kev=0.0, quiet=False)
+    g = picgen.Grid(nx=nx, nz=nz, dx=1.25, dz=1.25, dt=0.5, h0=(0.0, 0.0, 0.5))
+    return picgen.Workload(name=f"warm{nx}x{nz}_Te{temperature_kev:g}keV_ppc{ppc}", grid=g,
+                           species=[el, io], steps=0, note="periodic warm plasma")
+
+
+def mover_options(binding, torch, steps):
+    """The mover options (the Lorentz-factor predictor gamma(u^n + beta E^n), bilinear B, both)
+    against the default mover: relative change of the total energy of periodic warm plasmas over
+    `steps` cycles (the diagnostic for choosing between the readings; a periodic plasma without
+    sources should keep its energy), and the cycle time on the foil (the per-particle kernel of
+    the options against the tile kernel)."""
+    names = {0: "default", 1: "gamma_predict", 2: "b_bilinear", 3: "both"}
+    res = {"energy": [], "foil_ms_per_cycle": {}}
+    for te in (1.0, 50.0):
+        wl = warm_plasma(te)
+        row = {"workload": wl.name, "cycles": steps, "particles": wl.n_particles}
+        for opt, nm in names.items():
+            ctx = binding.Context(wl.grid)
+            for s, sp in enumerate(wl.species):
+                ctx.load_particles(s, sp.q, sp.m, sp.w, sp.xi_x, sp.xi_z, sp.ux, sp.uy, sp.uz)
+            ctx.set_mover(opt)
+            E0 = ctx.energy()
+            W0, K0 = sum(E0), sum(E0[1:])
+            worst = 0.0
+            done = 0
+            while done < steps:
+                k = min(100, steps - done)
+                ctx.step(k)
+                done += k
+                worst = max(worst, abs(sum(ctx.energy()) - W0) / K0)
+            W1 = ctx.energy()
+            # the uniform B_z holds most of the field energy: changes are given relative to the
+            # initial kinetic energy as well as to the total
+            row[nm] = {"energy_start": E0, "energy_end": W1,
+                       "total_change_over_total": (sum(W1) - W0) / W0,
+                       "total_change_over_kinetic0": (sum(W1) - W0) / K0,
+                       "max_abs_change_over_kinetic0": worst,
+                       "kinetic_end_over_kinetic0": sum(W1[1:]) / K0}
+            ctx.close()
+        res["energy"].append(row)
+    wl = picgen.named("foil")
+    for opt, nm in names.items():
+        ctx = binding.Context(wl.grid, tile=(32, 2))
+        for s, sp in enumerate(wl.species):
+            ctx.load_particles(s, sp.q, sp.m, sp.w, sp.xi_x, sp.xi_z, sp.ux, sp.uy, sp.uz)
+        ctx.set_mover(opt)
+        ctx.step(2)
+        ctx.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.step(10)
+        ctx.sync()
+        res["foil_ms_per_cycle"][nm] = 1e3 * (time.perf_counter() - t0) / 10
+        ctx.close()
+    return res
+
+
 def serving(args):
     """The batched serving stream: independent foil runs arriving Poisson at serve_rate per
     second (grid sides log-uniform in [32, 512], slab 5-15 % of x, density 10-200 n_c,
@@ -335,6 +404,9 @@ def main():
     if args.drift_steps > 0:
         out["precision_drift"] = drift(binding, args.drift_steps)
         print("[bench] drift done", file=sys.stderr, flush=True)
+    if args.mover_steps > 0:
+        out["mover_options"] = mover_options(binding, torch, args.mover_steps)
+        print("[bench] mover options done", file=sys.stderr, flush=True)
     if args.serve_runs > 0:
         out["serving"] = serving(args)
         print("[bench] serving done", file=sys.stderr, flush=True)

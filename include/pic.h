@@ -67,6 +67,16 @@ typedef enum {
 
 enum { PIC_BC_PERIODIC = 0, PIC_BC_ABSORBING = 1 };
 enum { PIC_PREC_FP64 = 0, PIC_PREC_MIXED = 1 };
+
+/* Mover options (bits of pic_set_mover's argument), two readings of what the paper leaves
+ * open, for comparing their energy behaviour:
+ *   PIC_MOVER_GAMMA_PREDICT  the Lorentz factor inside the linearised mover is
+ *                            gamma(u^n + beta E^n), E^n interpolated at the particle (a
+ *                            Boris-style predictor), instead of gamma(u^n);
+ *   PIC_MOVER_B_BILINEAR     B at the particle is interpolated bilinearly from the four
+ *                            surrounding cell centres (the edge cell repeated beyond an
+ *                            absorbing x boundary), instead of its own cell's H. */
+enum { PIC_MOVER_GAMMA_PREDICT = 1, PIC_MOVER_B_BILINEAR = 2 };
 enum { PIC_MAX_SPECIES = 8 };
 
 /* Device overflow flags reported in pic_info.overflow_flags. */
@@ -185,6 +195,23 @@ pic_status pic_sync(pic_ctx *ctx);
  * the timed cycles only, with pic_profile_read (waits for the stream). */
 pic_status pic_profile_enable(pic_ctx *ctx, int32_t on);
 pic_status pic_profile_read(pic_ctx *ctx, pic_profile *out);
+
+/* Select the mover options (PIC_MOVER_* bits; 0 restores the default mover).  Both the
+ * deposit (Step 1) and the push of every later cycle use them.  With any option set, the
+ * particle stage of a cycle runs in a kernel with one thread per particle that deposits each
+ * particle's expanded moments with global atomics (per-particle B makes S-hat differ from
+ * particle to particle): slower than the default tile kernel.  If particles are loaded, the
+ * moments of the current state are deposited again with the new options.  Errors:
+ * PIC_ERR_ARG (unknown bits, or a mixed-precision context: the options are FP64 only),
+ * PIC_ERR_STATE (the context is in a batch). */
+pic_status pic_set_mover(pic_ctx *ctx, int32_t options);
+
+/* Energies of the current state, computed on the device: out[0] = field energy
+ * (1/2)(sum over nodes of |E^n|^2 + sum over cells of |H^{n+1/2}|^2) dx dz, out[1 + s] =
+ * kinetic energy of species s, sum over its particles of w m (gamma(u^n) - 1) dx dz (0 for a
+ * species without particles).  len >= 1 + n_species.  Waits for the stream.  Errors:
+ * PIC_ERR_ARG (out NULL or len too small). */
+pic_status pic_energy(pic_ctx *ctx, double *out, int32_t len);
 
 /* Message for the last failed call on this context (or of pic_init_grid when ctx is NULL). */
 const char *pic_last_error(const pic_ctx *ctx);

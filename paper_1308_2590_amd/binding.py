@@ -19,10 +19,13 @@ PIC_OK = 0
 STATUS = {0: "PIC_OK", 1: "PIC_ERR_ARG", 2: "PIC_ERR_OOM", 3: "PIC_ERR_DEVICE",
           4: "PIC_ERR_STATE", 5: "PIC_ERR_RANGE", 6: "PIC_ERR_OVERFLOW"}
 MAX_SPECIES = 8
+MOVER_GAMMA_PREDICT = 1   # gamma-bar = gamma(u^n + beta E^n) (Boris-style predictor)
+MOVER_B_BILINEAR = 2      # B interpolated from the four surrounding cell centres
 EXPORTED = ["pic_init_grid", "pic_load_particles", "pic_load_fields", "pic_set_tiles",
             "pic_set_step", "pic_step",
             "pic_read_moments", "pic_read_fields", "pic_read_particles", "pic_get_info",
             "pic_set_stream", "pic_sync", "pic_profile_enable", "pic_profile_read",
+            "pic_set_mover", "pic_energy",
             "pic_last_error", "pic_destroy",
             "pic_batch_create", "pic_batch_add", "pic_batch_remove", "pic_batch_step",
             "pic_batch_set_graph", "pic_batch_sync", "pic_batch_size", "pic_batch_last_error",
@@ -96,6 +99,8 @@ def load_library(path: str = LIB_PATH):
         "pic_sync": ([P], C.c_int),
         "pic_profile_enable": ([P, I32], C.c_int),
         "pic_profile_read": ([P, C.POINTER(Profile)], C.c_int),
+        "pic_set_mover": ([P, I32], C.c_int),
+        "pic_energy": ([P, P, I32], C.c_int),
         "pic_last_error": ([P], C.c_char_p),
         "pic_destroy": ([P], None),
         "pic_batch_create": ([I32, I32, C.POINTER(P)], C.c_int),
@@ -203,6 +208,16 @@ class Context:
 
     def set_tiles(self, tile_x, tile_z):
         self._check(self.lib.pic_set_tiles(self.h, int(tile_x), int(tile_z)))
+
+    def set_mover(self, options):
+        """MOVER_* bits (0: the default mover); FP64 contexts only."""
+        self._check(self.lib.pic_set_mover(self.h, int(options)))
+
+    def energy(self):
+        """[field energy, kinetic energy of species 0, 1, ...] of the current state."""
+        out = np.zeros(1 + self.S)
+        self._check(self.lib.pic_energy(self.h, _p(out), len(out)))
+        return [float(v) for v in out]
 
     def set_step(self, step):
         self._check(self.lib.pic_set_step(self.h, int(step)))

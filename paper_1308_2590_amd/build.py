@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpic.so")
-SOURCES = ["pic_kernels.hip", "pic_capi.cpp", "pic_batch.cpp"]
+SOURCES = ["pic_kernels.hip", "pic_alt.hip", "pic_capi.cpp", "pic_batch.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

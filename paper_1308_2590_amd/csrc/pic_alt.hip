@@ -1,0 +1,291 @@
+// HIP kernels (gfx950) for the mover options and the energy diagnostic.
+//
+//   k_particles_alt  the particle stage of a cycle with a mover option (FP64): one thread per
+//                    sorted slot; gather E-bar (bilinear from the 4 corner nodes), B at the
+//                    particle (its cell's H, or bilinear from the 4 surrounding cell centres),
+//                    gamma-bar (gamma(u^n), or gamma(u^n + beta E^n) with E^n interpolated at
+//                    the particle), the implicit push of Eq. (2), position advance and move
+//                    code, then the deposit of S-hat, delta-j and density (Step 1, Eq. (3)) at
+//                    the new position with the same options, straight into the global moment
+//                    planes with FP64 atomics.  It writes the move codes, counts and arrivals
+//                    the cycle's sort reads, exactly as the tile kernel does.  Without push it
+//                    deposits the current state.
+//   k_energy         field energy (1/2)(sum |E|^2 over nodes + sum |H|^2 over cells) dx dz and
+//                    kinetic energy sum w m (gamma - 1) dx dz per species.
+//
+// The options are two readings of what the paper leaves open (the Lorentz factor inside the
+// linearised mover and B at a particle when H is cell-centred).  Per-particle B makes S-hat
+// differ from particle to particle, so these kernels deposit each particle's expanded moments
+// instead of per-cell sums; they trade speed for the choice.
+
+#include "pic_internal.h"
+
+namespace pic {
+namespace {
+
+constexpr uint32_t kFlagNonFiniteA = PIC_FLAG_NONFINITE;
+constexpr uint32_t kFlagJumpA = PIC_FLAG_JUMP;
+constexpr uint32_t kFlagOrderA = PIC_FLAG_ORDER;
+
+__device__ __forceinline__ int wrapc(int i, int n) {
+  if (i < 0) return i + n;
+  if (i >= n) return i - n;
+  return i;
+}
+
+// The four corner nodes of cell (i, k) (order (i,k), (i+1,k), (i,k+1), (i+1,k+1)) and the
+// linear weights of offsets (fx, fz).
+__device__ __forceinline__ void corners(const GridArgs &g, int i, int k, double fx, double fz,
+                                        int64_t node[4], double W[4]) {
+  const int i1 = g.bc_x == PIC_BC_PERIODIC ? wrapc(i + 1, g.nx) : i + 1;
+  const int k1 = wrapc(k + 1, g.nz);
+  node[0] = (int64_t)k * g.nxn + i;
+  node[1] = (int64_t)k * g.nxn + i1;
+  node[2] = (int64_t)k1 * g.nxn + i;
+  node[3] = (int64_t)k1 * g.nxn + i1;
+  W[0] = (1.0 - fx) * (1.0 - fz);
+  W[1] = fx * (1.0 - fz);
+  W[2] = (1.0 - fx) * fz;
+  W[3] = fx * fz;
+}
+
+__device__ __forceinline__ double at_nodes(const double *f, const int64_t node[4], const double W[4]) {
+  return W[0] * f[node[0]] + W[1] * f[node[1]] + W[2] * f[node[2]] + W[3] * f[node[3]];
+}
+
+// B at position (x, z) in cell (i, k) from the cell-centred planes H.
+__device__ void b_at(const GridArgs &g, const double *H, int mover, double x, double z, int i,
+                     int k, double B[3]) {
+  const int64_t nc = g.ncells;
+  if (!(mover & PIC_MOVER_B_BILINEAR)) {
+    const int64_t c = (int64_t)k * g.nx + i;
+    for (int r = 0; r < 3; ++r) B[r] = H[r * nc + c];
+    return;
+  }
+  const double sx = x - 0.5, sz = z - 0.5;
+  const int ic = (int)floor(sx), kc = (int)floor(sz);
+  const double gx = sx - (double)ic, gz = sz - (double)kc;
+  int ci[2], ck[2];
+  for (int t = 0; t < 2; ++t) {
+    const int ii = ic + t;
+    ci[t] = g.bc_x == PIC_BC_PERIODIC ? wrapc(ii, g.nx) : min(max(ii, 0), g.nx - 1);
+    ck[t] = wrapc(kc + t, g.nz);
+  }
+  const double Wc[4] = {(1.0 - gx) * (1.0 - gz), gx * (1.0 - gz), (1.0 - gx) * gz, gx * gz};
+  const int64_t c4[4] = {(int64_t)ck[0] * g.nx + ci[0], (int64_t)ck[0] * g.nx + ci[1],
+                         (int64_t)ck[1] * g.nx + ci[0], (int64_t)ck[1] * g.nx + ci[1]};
+  for (int r = 0; r < 3; ++r)
+    B[r] = Wc[0] * H[r * nc + c4[0]] + Wc[1] * H[r * nc + c4[1]] + Wc[2] * H[r * nc + c4[2]] +
+           Wc[3] * H[r * nc + c4[3]];
+}
+
+// gamma-bar for momentum u at a particle with corner nodes/weights: gamma(u), or with the
+// predictor gamma(u + beta E) for E interpolated from the planes En.
+__device__ double gamma_bar(const GridArgs &g, const double *En, int mover, double beta,
+                            const double u[3], const int64_t node[4], const double W[4]) {
+  if (!(mover & PIC_MOVER_GAMMA_PREDICT)) return sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  double um[3];
+  for (int r = 0; r < 3; ++r) um[r] = u[r] + beta * at_nodes(En + r * g.nnodes, node, W);
+  return sqrt(1.0 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+}
+
+// Deposit one particle's S-hat (9), delta-j (3) and density at its corner nodes: with
+// s = beta / gamma-bar and D = 1 + s^2 B.B, S-hat = (w q^2 dt^2 / (4 m gamma-bar D)) (I + s [B]x
+// + s^2 B B^T) and delta-j = (w q / (gamma-bar D)) (u + s u x B + s^2 (B.u) B).
+__device__ void deposit_one(const StepArgs &a, const SpeciesArgs &sp, int s, double gam,
+                            const double u[3], const double B[3], const int64_t node[4],
+                            const double W[4]) {
+  const double sg = sp.beta / gam;
+  const double inv = 1.0 / (1.0 + sg * sg * (B[0] * B[0] + B[1] * B[1] + B[2] * B[2]));
+  const double a0 = sp.cS / gam * inv, a1 = a0 * sg, a2 = a1 * sg;
+  const double kk = sp.kJ / gam * inv;
+  const double bu = B[0] * u[0] + B[1] * u[1] + B[2] * u[2];
+  double v[13];
+  v[0] = a2 * B[0] * B[0] + a0;
+  v[1] = a2 * B[0] * B[1] + a1 * B[2];
+  v[2] = a2 * B[0] * B[2] - a1 * B[1];
+  v[3] = a2 * B[1] * B[0] - a1 * B[2];
+  v[4] = a2 * B[1] * B[1] + a0;
+  v[5] = a2 * B[1] * B[2] + a1 * B[0];
+  v[6] = a2 * B[2] * B[0] + a1 * B[1];
+  v[7] = a2 * B[2] * B[1] - a1 * B[0];
+  v[8] = a2 * B[2] * B[2] + a0;
+  v[9] = kk * (u[0] + sg * (u[1] * B[2] - u[2] * B[1]) + sg * sg * bu * B[0]);
+  v[10] = kk * (u[1] + sg * (u[2] * B[0] - u[0] * B[2]) + sg * sg * bu * B[1]);
+  v[11] = kk * (u[2] + sg * (u[0] * B[1] - u[1] * B[0]) + sg * sg * bu * B[2]);
+  v[12] = sp.w;
+  const int64_t nn = a.g.nnodes;
+  for (int c = 0; c < 4; ++c) {
+    for (int r = 0; r < 12; ++r) unsafeAtomicAdd(&a.M[(int64_t)r * nn + node[c]], W[c] * v[r]);
+    unsafeAtomicAdd(&a.M[(int64_t)(12 + s) * nn + node[c]], W[c] * v[12]);
+  }
+}
+
+template <bool PUSH>
+__global__ __launch_bounds__(kBlock) void k_particles_alt(const StepArgs a, int mover) {
+  const GridArgs &g = a.g;
+  // the next order's tile flags are set by the sort's scan; every tile may hold deposits
+  if (blockIdx.y == 0) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < a.t.ntiles; t += gridDim.x * blockDim.x) {
+      if (PUSH) a.tile_active_next[t] = 0;
+      if (a.mtile) a.mtile[t] = 1;
+    }
+  }
+  const int s = blockIdx.y;
+  const SpeciesArgs &sp = a.sp[s];
+  if (!sp.active) return;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = sp.cs[g.ncells];
+  if (j >= n) return;
+  const int p = sp.perm[j];
+  const double x = sp.src[0][p], z = sp.src[1][p];
+  const double u[3] = {sp.src[2][p], sp.src[3][p], sp.src[4][p]};
+  const int i = (int)floor(x), k = (int)floor(z);
+  if (i < 0 || i >= g.nx || k < 0 || k >= g.nz) {
+    atomicOr(a.flags, kFlagOrderA);
+    if (PUSH) sp.locode[j] = ((uint32_t)j << 4) | kAbsorbed;
+    return;
+  }
+  int64_t node[4];
+  double W[4];
+  corners(g, i, k, x - (double)i, z - (double)k, node, W);
+  double B[3];
+  b_at(g, a.Hold, mover, x, z, i, k, B);
+  const double gam = gamma_bar(g, a.Eold, mover, sp.beta, u, node, W);
+  if (!PUSH) {
+    deposit_one(a, sp, s, gam, u, B, node, W);
+    return;
+  }
+  // E-bar at the particle and the implicit push: a = u + beta E-bar, b = beta B / gamma-bar,
+  // u-bar = (a + a x b + (a.b) b) / (1 + b.b), u' = 2 u-bar - u
+  const int64_t nn = g.nnodes;
+  double Eb[3];
+  for (int r = 0; r < 3; ++r) {
+    const double *eo = a.Eold + r * nn, *en = a.Enew + r * nn;
+    double acc = 0.0;
+    for (int c = 0; c < 4; ++c) acc += W[c] * (0.5 * (eo[node[c]] + en[node[c]]));
+    Eb[r] = acc;
+  }
+  const double bx = sp.beta / gam * B[0], by = sp.beta / gam * B[1], bz = sp.beta / gam * B[2];
+  const double a0 = u[0] + sp.beta * Eb[0], a1 = u[1] + sp.beta * Eb[1], a2 = u[2] + sp.beta * Eb[2];
+  const double inv = 1.0 / (1.0 + bx * bx + by * by + bz * bz);
+  const double ab = a0 * bx + a1 * by + a2 * bz;
+  double un[3];
+  un[0] = 2.0 * ((a0 + (a1 * bz - a2 * by) + ab * bx) * inv) - u[0];
+  un[1] = 2.0 * ((a1 + (a2 * bx - a0 * bz) + ab * by) * inv) - u[1];
+  un[2] = 2.0 * ((a2 + (a0 * by - a1 * bx) + ab * bz) * inv) - u[2];
+  const double g1 = sqrt(1.0 + un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
+  double xn = x + g.cx * (un[0] / g1), zn = z + g.cz * (un[2] / g1);
+  bool alive = true;
+  if (g.bc_x == PIC_BC_PERIODIC) {
+    if (xn < 0.0) xn += (double)g.nx;
+    if (xn >= (double)g.nx) xn -= (double)g.nx;
+  } else if (xn < 0.0 || xn >= (double)g.nx) {
+    alive = false;
+  }
+  if (zn < 0.0) zn += (double)g.nz;
+  if (zn >= (double)g.nz) zn -= (double)g.nz;
+  const bool finite = isfinite(g1) && isfinite(xn) && isfinite(zn);
+  if (!finite) atomicOr(a.flags, kFlagNonFiniteA);
+  alive = alive && finite;
+  const int i2 = finite ? (int)floor(xn) : i, k2 = finite ? (int)floor(zn) : k;
+  int di = i2 - i, dk = k2 - k;
+  if (di > 1) di -= g.nx;
+  if (di < -1) di += g.nx;
+  if (dk > 1) dk -= g.nz;
+  if (dk < -1) dk += g.nz;
+  const bool jump = di < -1 || di > 1 || dk < -1 || dk > 1;
+  if (alive && jump) atomicOr(a.flags, kFlagJumpA);
+  alive = alive && !jump;
+  const uint32_t code = alive ? (uint32_t)((dk + 1) * 3 + (di + 1)) : kAbsorbed;
+  // the pushed state goes to location j of the other buffer; the sort reads the codes
+  sp.dst[0][j] = xn;
+  sp.dst[1][j] = zn;
+  sp.dst[2][j] = un[0];
+  sp.dst[3][j] = un[1];
+  sp.dst[4][j] = un[2];
+  if (sp.dst_id) sp.dst_id[j] = sp.src_id[p];
+  sp.locode[j] = ((uint32_t)j << 4) | code;
+  if (!alive) return;
+  atomicAdd(&sp.cnt[(int64_t)code * g.ncells + (int64_t)k * g.nx + i], 1);
+  atomicAdd(&sp.arr[(int64_t)k2 * g.nx + i2], 1);
+  // the moments at x^{n+3/2} with u^{n+1}, B = H^{n+3/2} at the new position and E^{n+1}
+  int64_t node2[4];
+  double W2[4], B2[3];
+  corners(g, i2, k2, xn - (double)i2, zn - (double)k2, node2, W2);
+  b_at(g, a.Hnew, mover, xn, zn, i2, k2, B2);
+  const double gam2 = gamma_bar(g, a.Enew, mover, sp.beta, un, node2, W2);
+  deposit_one(a, sp, s, gam2, un, B2, node2, W2);
+}
+
+// Energies: out[0] field, out[1 + s] kinetic of species s (both times dx dz), summed over
+// blocks with FP64 atomics.
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+  __syncthreads();
+  return t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_energy(const StepArgs a, const double *E,
+                                                   const double *H, double *out) {
+  __shared__ double sh[kBlock / 64];
+  const GridArgs &g = a.g;
+  const double area = g.dx * g.dz;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  double f = 0.0;
+  for (int64_t e = tid; e < 3 * g.nnodes; e += stride) f += E[e] * E[e];
+  for (int64_t e = tid; e < 3 * g.ncells; e += stride) f += H[e] * H[e];
+  const double fs = block_sum(f, sh);
+  if (threadIdx.x == 0) unsafeAtomicAdd(&out[0], 0.5 * fs * area);
+  for (int s = 0; s < a.nsp; ++s) {
+    const SpeciesArgs &sp = a.sp[s];
+    if (!sp.active) continue;
+    const int n = sp.cs[g.ncells];
+    double kin = 0.0;
+    for (int64_t j = tid; j < n; j += stride) {
+      const int p = sp.perm[j];
+      double u0, u1, u2;
+      if (a.mixed) {
+        u0 = (double)sp.msrc[2][p];
+        u1 = (double)sp.msrc[3][p];
+        u2 = (double)sp.msrc[4][p];
+      } else {
+        u0 = sp.src[2][p];
+        u1 = sp.src[3][p];
+        u2 = sp.src[4][p];
+      }
+      kin += sqrt(1.0 + u0 * u0 + u1 * u1 + u2 * u2) - 1.0;
+    }
+    const double ks = block_sum(kin, sh);
+    if (threadIdx.x == 0) unsafeAtomicAdd(&out[1 + s], ks * sp.w * sp.m * area);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_particles_alt(const StepArgs &a, bool push, int mover, int32_t max_n,
+                                hipStream_t s) {
+  const unsigned nb = (unsigned)std::max<int64_t>(
+      1, std::max<int64_t>((max_n + kBlock - 1) / kBlock, (a.t.ntiles + kBlock - 1) / kBlock));
+  const dim3 grid(nb, (unsigned)a.nsp);
+  if (push)
+    hipLaunchKernelGGL(k_particles_alt<true>, grid, dim3(kBlock), 0, s, a, mover);
+  else
+    hipLaunchKernelGGL(k_particles_alt<false>, grid, dim3(kBlock), 0, s, a, mover);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy(const StepArgs &a, const double *E, const double *H, double *out,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_energy, dim3(1024), dim3(kBlock), 0, s, a, E, H, out);
+  return hipGetLastError();
+}
+
+}  // namespace pic

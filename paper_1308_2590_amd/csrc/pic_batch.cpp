@@ -225,6 +225,7 @@ pic_status pic_batch_add(pic_batch *b, pic_ctx *c) {
   if (c->batch) return bfail(b, PIC_ERR_ARG, "the context is already in a batch");
   if (c->d.device != b->device) return bfail(b, PIC_ERR_ARG, "the context is on another device");
   if (c->d.precision != b->precision) return bfail(b, PIC_ERR_ARG, "the context has another precision");
+  if (c->mover != 0) return bfail(b, PIC_ERR_ARG, "contexts with mover options are not batched");
   bool any = false;
   for (int s = 0; s < c->S; ++s) any = any || c->sp[s].loaded;
   if (!any) return bfail(b, PIC_ERR_ARG, "the context has no particles");

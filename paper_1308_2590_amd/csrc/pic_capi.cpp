@@ -70,7 +70,7 @@ void free_species(pic_ctx *c, SpeciesState &s) {
     for (int v = 0; v < 5; ++v) dfree(c, s.mbuf[b][v], cap * sizeof(float)), s.mbuf[b][v] = nullptr;
     dfree(c, s.mcell[b], cap * sizeof(int32_t)), s.mcell[b] = nullptr;
     dfree(c, s.ids[b], cap * sizeof(int64_t)), s.ids[b] = nullptr;
-    dfree(c, s.perm[b], cap * sizeof(int32_t)), s.perm[b] = nullptr;
+    dfree(c, s.perm[b], (cap + pic::kPermPad) * sizeof(int32_t)), s.perm[b] = nullptr;
     dfree(c, s.cs[b], (nc + 1) * sizeof(int32_t)), s.cs[b] = nullptr;
   }
   dfree(c, s.locode, cap * sizeof(uint32_t)), s.locode = nullptr;
@@ -121,6 +121,7 @@ pic::StepArgs step_args(pic_ctx *c, bool push) {
     pic::SpeciesArgs &x = a.sp[s];
     x.active = st.loaded ? 1 : 0;
     if (!st.loaded) continue;
+    x.cap = (int32_t)st.cap;
     x.q = st.q;
     x.m = st.m;
     x.w = st.w;
@@ -203,6 +204,14 @@ pic_status build_tile_list(pic_ctx *c) {
   return PIC_OK;
 }
 
+// Largest particle capacity of the loaded species (bounds the per-particle kernel's grid).
+int32_t max_particles(const pic_ctx *c) {
+  int64_t m = 0;
+  for (int s = 0; s < c->S; ++s)
+    if (c->sp[s].loaded) m = std::max<int64_t>(m, c->sp[s].cap);
+  return (int32_t)m;
+}
+
 // Deposit M^{k+1/2} of the current state (used after loads).
 pic_status redeposit(pic_ctx *c) {
   HIP_TRY(c, hipMemsetAsync(c->M, 0, (size_t)c->g.n_planes * c->g.nnodes * sizeof(double), c->stream),
@@ -214,11 +223,29 @@ pic_status redeposit(pic_ctx *c) {
   if (rs != PIC_OK) return rs;
   if ((rs = build_tile_list(c)) != PIC_OK) return rs;
   pic::StepArgs a = step_args(c, false);
-  a.Eold = a.Enew = c->E[c->ecur];  // not read by a deposit
+  a.Eold = a.Enew = c->E[c->ecur];  // E^n: read by the gamma-bar predictor of the options only
   a.Hold = c->H[c->hcur];
   a.Hnew = c->H[c->hcur];
   a.M = c->M;
-  HIP_TRY(c, pic::launch_particles(a, false, c->stream), "deposit kernel");
+  if (c->mover)
+    HIP_TRY(c, pic::launch_particles_alt(a, false, c->mover, max_particles(c), c->stream), "deposit kernel");
+  else
+    HIP_TRY(c, pic::launch_particles(a, false, c->stream), "deposit kernel");
+  return PIC_OK;
+}
+
+// The particle stage of one cycle: the tile kernel, or with mover options the per-particle
+// kernel (whose move counts are accumulated from zero).
+pic_status particle_stage(pic_ctx *c, const pic::StepArgs &a) {
+  if (!c->mover) {
+    HIP_TRY(c, pic::launch_particles(a, true, c->stream), "particle kernel");
+    return PIC_OK;
+  }
+  for (int s = 0; s < c->S; ++s)
+    if (c->sp[s].loaded)
+      HIP_TRY(c, hipMemsetAsync(c->sp[s].cnt, 0, (size_t)pic::kMoveCodes * c->g.ncells * sizeof(int32_t),
+                                c->stream), "clear move counts");
+  HIP_TRY(c, pic::launch_particles_alt(a, true, c->mover, max_particles(c), c->stream), "particle kernel");
   return PIC_OK;
 }
 
@@ -463,7 +490,10 @@ pic_status pic_load_particles(pic_ctx *c, int32_t s, double q, double m, double 
     }
     if (c->d.track_ids)
       if ((rs = dalloc(c, &st.ids[b], cap, "alloc ids")) != PIC_OK) return rs;
-    if ((rs = dalloc(c, &st.perm[b], cap, "alloc perm")) != PIC_OK) return rs;
+    // padded: the particle kernel reads the permutation 4 entries at a time, up to 7 past
+    // the last slot of a row part
+    if ((rs = dalloc(c, &st.perm[b], cap + pic::kPermPad, "alloc perm")) != PIC_OK) return rs;
+    HIP_TRY(c, hipMemset(st.perm[b], 0, (cap + pic::kPermPad) * sizeof(int32_t)), "clear perm");
     if ((rs = dalloc(c, &st.cs[b], (size_t)nc + 1, "alloc cell starts")) != PIC_OK) return rs;
   }
   if ((rs = dalloc(c, &st.locode, cap, "alloc codes")) != PIC_OK) return rs;
@@ -600,7 +630,8 @@ pic_status pic_step(pic_ctx *c, int32_t nsteps) {
     HIP_TRY(c, pic::launch_field_solve(fa, c->stream), "field solve");
     if (pe) HIP_TRY(c, hipEventRecord(pe->ev[1], c->stream), "event record");
     const pic::StepArgs a = pic::cycle_step_args(c, c->cur);
-    HIP_TRY(c, pic::launch_particles(a, true, c->stream), "particle kernel");
+    pic_status ps = particle_stage(c, a);
+    if (ps != PIC_OK) return ps;
     if (pe) HIP_TRY(c, hipEventRecord(pe->ev[2], c->stream), "event record");
     HIP_TRY(c, pic::launch_sort(a, c->stream), "sort kernels");
     if (pe) HIP_TRY(c, hipEventRecord(pe->ev[3], c->stream), "event record");
@@ -758,6 +789,32 @@ pic_status pic_profile_read(pic_ctx *c, pic_profile *out) {
   HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
   prof_accumulate(c);
   *out = c->prof_acc;
+  return PIC_OK;
+}
+
+pic_status pic_set_mover(pic_ctx *c, int32_t options) {
+  if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
+  if (options & ~(PIC_MOVER_GAMMA_PREDICT | PIC_MOVER_B_BILINEAR))
+    return fail(c, PIC_ERR_ARG, "unknown mover option bits");
+  if (options && mixed(c)) return fail(c, PIC_ERR_ARG, "mover options are for FP64 contexts only");
+  if (c->batch) return fail(c, PIC_ERR_STATE, "the context is stepped by a batch");
+  c->mover = options;
+  return redeposit(c);
+}
+
+pic_status pic_energy(pic_ctx *c, double *out, int32_t len) {
+  if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
+  if (!out || len < 1 + c->S) return fail(c, PIC_ERR_ARG, "out must hold 1 + n_species values");
+  double *d = nullptr;
+  pic_status st = dalloc(c, &d, (size_t)1 + c->S, "alloc energy");
+  if (st != PIC_OK) return st;
+  pic::StepArgs a = step_args(c, false);
+  hipError_t e = hipMemsetAsync(d, 0, (1 + (size_t)c->S) * sizeof(double), c->stream);
+  if (e == hipSuccess) e = pic::launch_energy(a, c->E[c->ecur], c->H[c->hcur], d, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = hipMemcpy(out, d, (1 + (size_t)c->S) * sizeof(double), hipMemcpyDeviceToHost);
+  dfree(c, d, (1 + (size_t)c->S) * sizeof(double));
+  if (e != hipSuccess) return hip_fail(c, e, "energy");
   return PIC_OK;
 }
 

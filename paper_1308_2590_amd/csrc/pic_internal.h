@@ -13,6 +13,7 @@ constexpr int kMaxSpecies = PIC_MAX_SPECIES;
 constexpr int kMoveCodes = 9;      // destination cell relative to the source: 3 x 3 block
 constexpr uint8_t kAbsorbed = 9;   // move code of a particle that left an absorbing boundary
 constexpr int kBlock = 256;        // threads per block of the tile kernels (4 wavefronts)
+constexpr int kPermPad = 8;        // padding entries after each permutation array
 constexpr int kSolveNodes = 2;     // nodes per thread in the E solve
 constexpr int kHCells = 2;         // cells per thread in the H update
 constexpr int kScanItems = 4;      // cells per thread in the count scan
@@ -61,6 +62,7 @@ struct SpeciesArgs {
   int32_t *cnt;              // [9][ncells] particles leaving each cell per move code
   int32_t *arr;              // [ncells] particles arriving in each cell; zero between cycles
   int32_t *bsum;             // block sums of the count scan
+  int32_t cap;               // particle capacity of the state arrays
   int32_t active;
 };
 
@@ -141,6 +143,13 @@ hipError_t launch_field_solve(const FieldArgs &a, hipStream_t s);
 // launch_sort is the sort of a cycle (two-pass scan with tile flags and list, then ranks).
 hipError_t launch_particles(const StepArgs &a, bool push, hipStream_t s);
 hipError_t launch_sort(const StepArgs &a, hipStream_t s);
+// The particle stage with mover options (PIC_MOVER_* bits), one thread per slot: max_n bounds
+// the particles of every species; the move counts must be zero on entry.
+hipError_t launch_particles_alt(const StepArgs &a, bool push, int mover, int32_t max_n,
+                                hipStream_t s);
+// Field and kinetic energies into out[1 + nsp] (accumulated: zero it first).
+hipError_t launch_energy(const StepArgs &a, const double *E, const double *H, double *out,
+                         hipStream_t s);
 hipError_t launch_iota(int32_t *p, int64_t n, hipStream_t s);
 // One cycle of every run of a batch (field solve, particles, sort, counters).
 hipError_t launch_batch_cycle(const BatchArgs &b, const BatchLaunch &l, hipStream_t s);

@@ -708,9 +708,20 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
       constexpr int kChunk = 4;
       Pstate<MIXED> cb[kChunk];
       int cp_[kChunk], np_[kChunk];
-      const int jlast = je - 1;
-#pragma unroll
-      for (int kk = 0; kk < kChunk; ++kk) np_[kk] = perm[min(start + kk, jlast)];
+      // A chunk's permutation entries come in one 16-byte load per lane (the array is padded
+      // so the load stays inside it); entries past the lane's run are clamped to a location
+      // inside the state arrays and their particles go unused.
+      static_assert(kChunk == 4 && kPermPad >= 2 * kChunk, "one int4 of entries per chunk");
+      const uint32_t loc_max = (uint32_t)(sp.cap - 1);
+      auto perm4 = [&](int first, int out[kChunk]) {
+        int4 v;
+        __builtin_memcpy(&v, perm + first, sizeof(v));
+        out[0] = (int)min((uint32_t)v.x, loc_max);
+        out[1] = (int)min((uint32_t)v.y, loc_max);
+        out[2] = (int)min((uint32_t)v.z, loc_max);
+        out[3] = (int)min((uint32_t)v.w, loc_max);
+      };
+      perm4(start, np_);
       // all lanes run the same number of iterations so the mover queue stays wave-uniform
       for (int c0 = 0; c0 < iters; c0 += kChunk) {
 #pragma unroll
@@ -718,8 +729,7 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
           cp_[kk] = np_[kk];
           cb[kk].load(src, cp_[kk]);
         }
-#pragma unroll
-        for (int kk = 0; kk < kChunk; ++kk) np_[kk] = perm[min(start + c0 + kChunk + kk, jlast)];
+        perm4(start + c0 + kChunk, np_);
 #pragma unroll
         for (int kk = 0; kk < kChunk; ++kk) {
           const int it = c0 + kk;
