@@ -703,8 +703,8 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
       // with loads, so a load whose value is still in flight across a loop iteration makes
       // the compiler wait for all earlier stores too; keeping every loaded value inside one
       // iteration lets it wait for the loads alone.  Loads are issued unconditionally (slots
-      // past a lane's run are clamped into the row, whose particles all exist, and their
-      // values go unused): a load under a divergent branch also forces a full wait.
+      // past a lane's run read a location inside the state arrays, and their values go
+      // unused): a load under a divergent branch also forces a full wait.
       constexpr int kChunk = 4;
       Pstate<MIXED> cb[kChunk];
       int cp_[kChunk], np_[kChunk];
