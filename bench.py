@@ -90,6 +90,9 @@ def parse():
                     help="timed cycles of each FP64 / mixed comparison run (0 skips them)")
     ap.add_argument("--drift-steps", type=int, default=500,
                     help="cycles of the FP64 / mixed drift comparison on the dense foil (0 skips it)")
+    ap.add_argument("--field-steps", type=int, default=20,
+                    help="timed cycles of the field-dominated run (2048 x 2048, 33.6M particles; "
+                         "0 skips it)")
     ap.add_argument("--mover-steps", type=int, default=1000,
                     help="cycles of the warm-plasma energy comparison of the mover options "
                          "(0 skips the mover-option section)")
@@ -250,6 +253,17 @@ def drift(binding, steps, name="foil_dense"):
             "mixed_vs_fp64_rounded_inputs": errs(runs["mixed"], runs["fp64_rounded_inputs"])}
 
 
+def field_dominated(binding, torch, steps, warmup):
+    """The field-dominated run (2048 x 2048 cells, uniform 0.1 n_c, 4 particles per cell and
+    species: 33.6M particles, laser a0 = 1) in FP64 with the library's tile choice: cycle time
+    and its split between the field solve, the particle kernel and the sort."""
+    wl = picgen.named("lowdensity")
+    m = run_gpu(binding, torch, wl, "fp64", steps, warmup, (0, 0))
+    return {"workload": wl.name, "particles": wl.n_particles, "cells": wl.grid.nx * wl.grid.nz,
+            "steps": steps, "ms_per_step": m["ms_per_step"], "particle_steps_per_s": m["value"],
+            "tile": m["tile"], "breakdown_ms_per_step": m["breakdown"]}
+
+
 def warm_plasma(temperature_kev, nx=128, nz=128, ppc=16):
     """Periodic two-species plasma with thermal electrons at temperature_kev (cold ions, m_i/m_e
     = 1836), density 1, dx = dz = 1.25, dt = 0.5 (omega_p dt = 0.5), uniform B_z = 0.5, E = 0."""
@@ -404,6 +418,9 @@ def main():
     if args.drift_steps > 0:
         out["precision_drift"] = drift(binding, args.drift_steps)
         print("[bench] drift done", file=sys.stderr, flush=True)
+    if args.field_steps > 0:
+        out["field_dominated"] = field_dominated(binding, torch, args.field_steps, args.warmup)
+        print("[bench] field-dominated run done", file=sys.stderr, flush=True)
     if args.mover_steps > 0:
         out["mover_options"] = mover_options(binding, torch, args.mover_steps)
         print("[bench] mover options done", file=sys.stderr, flush=True)

@@ -88,7 +88,7 @@ bool mixed(const pic_ctx *c) { return c->d.precision == PIC_PREC_MIXED; }
 // Tile size from the load.  One wavefront handles one row of a tile, each lane a contiguous
 // run of that row's particles, so a tile is 4 rows high and wide enough for a row to hold
 // about 1024 particles of a species (runs of ~16); a power of two in [4, 32], shrunk until
-// the LDS accumulators fit in 64 KiB (two blocks per CU).
+// two blocks fit in the LDS of a CU (half the LDS a block may use).
 void choose_tiles(pic_ctx *c, int64_t total, int64_t occupied, int nspecies) {
   int tx = c->d.tile_x, tz = c->d.tile_z;
   if (tx <= 0 || tz <= 0) {
@@ -96,7 +96,8 @@ void choose_tiles(pic_ctx *c, int64_t total, int64_t occupied, int nspecies) {
     tx = 4;
     while (tx < 32 && (double)(2 * tx) * ppc <= 1024.0 * 1.4) tx *= 2;
     tz = 4;
-    while (tx > 4 && pic::particle_lds_bytes(c->g, pic::TileArgs{tx, tz, 0, 0, 0, 0}, mixed(c)) > 65536)
+    while (tx > 4 &&
+           pic::particle_lds_bytes(c->g, pic::TileArgs{tx, tz, 0, 0, 0, 0}, mixed(c)) > c->lds_max / 2)
       tx /= 2;
   }
   c->tiles.tx = tx;

@@ -328,3 +328,20 @@ def test_foil_full_size_one_cycle(pic):
     assert info["overflow_flags"] == 0
     assert info["tile"] == info0["tile"]
     ctx.close()
+
+
+def test_field_dominated_full_size_one_cycle(pic):
+    """The field-dominated run (2048 x 2048 cells, 0.1 n_c, 4 particles per cell and species:
+    33.6M particles, with the laser entering at x = 0) at full size: the deposit of the loaded
+    state and one whole cycle (fields, moments, sorted particles) against the oracle."""
+    wl = picgen.named("lowdensity")
+    _say(f"field-dominated full size {wl.n_particles} particles")
+    ctx, orc = setup_both(pic, wl, track_ids=False)
+    check_moments(ctx, orc)
+    ctx.step(1)
+    orc.step(1)
+    check_fields(ctx, orc)
+    check_moments(ctx, orc)
+    check_particles(ctx, orc, wl, ids=False)
+    assert ctx.get_info()["overflow_flags"] == 0
+    ctx.close()
