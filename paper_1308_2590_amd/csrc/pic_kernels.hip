@@ -1205,10 +1205,10 @@ __device__ int dest_base(const GridArgs &g, int ic, int kc, int d, Cnt cntv, Csn
 }
 
 // Stable destinations of one tile's particles.  The destination base of every (cell, move
-// code) of the tile is computed once into LDS; then one wavefront per tile row walks the row's
-// slots in order, 64 at a time: particles with the same (cell, code) in a group of 64 get
-// consecutive ranks from per-code ballots, and a per-wave LDS counter carries the rank across
-// groups.
+// code) of the tile is computed once into LDS; then one wavefront per tile row (or part of a
+// row) walks the row's slots in order, 64 at a time: particles with the same (cell, code) in a
+// group of 64 get consecutive ranks from ballots of the code's bits, and a per-wave LDS
+// counter carries the rank across groups.
 __device__ __forceinline__ void rank_body(const StepArgs &a, int tile, int species) {
   const GridArgs &g = a.g;
   const TileArgs &t = a.t;
@@ -1233,6 +1233,19 @@ __device__ __forceinline__ void rank_body(const StepArgs &a, int tile, int speci
     const int s = species;
     const SpeciesArgs &sp = a.sp[s];
     if (!sp.active) return;
+    // A tile with fewer rows than wavefronts splits each row's slots into wpr contiguous
+    // parts, one per wavefront.  A part that starts inside a cell first counts, per move code,
+    // that cell's slots before the part, so its ranks continue the ones of the parts before.
+    const int nrows = k1 - k0;
+    const int wpr = nrows < nwaves ? nwaves / nrows : 1;
+    const int part = wave % wpr;
+    const int r_first = k0 + wave / wpr;
+    // the first row's cell starts and counters, loaded together with the staging below
+    if (r_first < k1) {
+      for (int q = lane; q <= cw; q += 64) rowcs[q] = sp.cs[(int64_t)r_first * g.nx + i0 + q];
+      for (int q = lane; q < cw * 10; q += 64) ctr[q] = 0;
+    }
+    const int total = sp.cs_new[g.ncells];
     // counts of the tile and a one-cell ring (sources of the destinations reached from the
     // tile), and next-order starts of the same region, staged in LDS
     const int RW = t.tx + 4, RH = t.tz + 4;  // ring of two cells: destinations +-1, their sources +-1
@@ -1249,14 +1262,8 @@ __device__ __forceinline__ void rank_body(const StepArgs &a, int tile, int speci
       rcsn[e] = in ? sp.cs_new[c] : 0;
     }
     __syncthreads();
-    // nothing to rank if no particle of this species leaves a cell of the tile alive
-    bool mine = false;
-    for (int e = threadIdx.x; e < ch * cw * kMoveCodes; e += blockDim.x) {
-      const int cell = e / kMoveCodes, d = e - cell * kMoveCodes;
-      const int lk = cell / cw, li = cell - lk * cw;
-      mine = mine || rcnt[d * RW * RH + (lk + 2) * RW + (li + 2)] > 0;
-    }
-    if (!__syncthreads_or(mine)) return;
+    // (a tile without particles of this species has no counts: its table stays zero and its
+    // rows are empty)
     // local ring coordinates of a global cell near the tile (periodic wrap on both axes)
     auto ring = [&](int gi, int gk) {
       int rx = gi - (i0 - 2), rz = gk - (k0 - 2);
@@ -1274,18 +1281,13 @@ __device__ __forceinline__ void rank_body(const StepArgs &a, int tile, int speci
       btab[(lk * t.tx + li) * kMoveCodes + d] = b;
     }
     __syncthreads();
-    const int total = sp.cs_new[g.ncells];
-    // A tile with fewer rows than wavefronts splits each row's slots into wpr contiguous
-    // parts, one per wavefront.  A part that starts inside a cell first counts, per move code,
-    // that cell's slots before the part, so its ranks continue the ones of the parts before.
-    const int nrows = k1 - k0;
-    const int wpr = nrows < nwaves ? nwaves / nrows : 1;
-    const int part = wave % wpr;
-    for (int r = k0 + wave / wpr; r < k1; r += nwaves / wpr) {
+    for (int r = r_first; r < k1; r += nwaves / wpr) {
       const int64_t rowc = (int64_t)r * g.nx;
       const int lk = r - k0;
-      for (int q = lane; q <= cw; q += 64) rowcs[q] = sp.cs[rowc + i0 + q];
-      for (int q = lane; q < cw * 10; q += 64) ctr[q] = 0;
+      if (r != r_first) {
+        for (int q = lane; q <= cw; q += 64) rowcs[q] = sp.cs[rowc + i0 + q];
+        for (int q = lane; q < cw * 10; q += 64) ctr[q] = 0;
+      }
       wave_sync();
       const int rb = rowcs[0], re = rowcs[cw];
       const int jb = rb + (int)((int64_t)(re - rb) * part / wpr);
@@ -1353,7 +1355,7 @@ __device__ __forceinline__ void rank_body(const StepArgs &a, int tile, int speci
           const bool valid = act && d < kMoveCodes;
           // The group's slots are in cell order, so the lanes of one cell are contiguous:
           // [cstart, cend).  A particle's rank within its (cell, code) in this group is the
-          // number of lanes of its cell below it with the same code (one ballot per code).
+          // number of lanes of its cell below it with the same code.
           const int prevcl = __shfl_up(cl, 1, 64);
           const uint64_t heads = __ballot(act && (lane == 0 || prevcl != cl));
           const uint64_t upto = heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
@@ -1361,11 +1363,13 @@ __device__ __forceinline__ void rank_body(const StepArgs &a, int tile, int speci
           const uint64_t above = heads & ~(lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
           const int cend = above ? __ffsll((unsigned long long)above) - 1 : 64;
           const uint64_t cellm = (cend == 64 ? ~0ull : ((1ull << cend) - 1ull)) & ~((1ull << cstart) - 1ull);
-          uint64_t same = 0;
+          // the lanes with the same move code: one ballot per bit of the code
+          uint64_t same = __ballot(valid);
 #pragma unroll
-          for (int dd = 0; dd < kMoveCodes; ++dd) {
-            const uint64_t m = __ballot(valid && d == dd);
-            if (d == dd) same = m;
+          for (int bit = 0; bit < 4; ++bit) {
+            const bool on = (d >> bit) & 1;
+            const uint64_t m = __ballot(valid && on);
+            same &= on ? m : ~m;
           }
           same &= cellm;
           if (valid) {
