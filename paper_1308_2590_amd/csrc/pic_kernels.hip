@@ -90,8 +90,7 @@ __device__ __forceinline__ double rsqT(double x) {
   return y;
 }
 __device__ __forceinline__ float rsqT(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double floorT(double a) { return floor(a); }
-__device__ __forceinline__ float floorT(float a) { return floorf(a); }
+__device__ __forceinline__ float floorT(float a) { return floorf(a); }  // the mixed carry (FP64 uses floor)
 
 // ------------------------------------------------------------------------------------------
 // Field solve
