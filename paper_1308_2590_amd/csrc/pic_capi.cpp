@@ -154,8 +154,6 @@ pic::StepArgs step_args(pic_ctx *c, bool push) {
   a.tile_active_next = c->tact[nxt];
   a.tile_list_next = c->tlist[nxt];
   a.mtile = c->mtile;
-  a.col_tile = c->col_tile;
-  a.row_tile = c->row_tile;
   return a;
 }
 
@@ -184,15 +182,6 @@ pic_status alloc_tiles(pic_ctx *c) {
   // cleared) by the next field solve.
   HIP_TRY(c, hipMemset(c->mtile, 1, (size_t)nt), "deposit flags");
   c->tiles_alloc = nt;
-  if (!c->col_tile) {
-    if ((st = dalloc(c, &c->col_tile, (size_t)c->g.nx, "alloc tile map")) != PIC_OK) return st;
-    if ((st = dalloc(c, &c->row_tile, (size_t)c->g.nz, "alloc tile map")) != PIC_OK) return st;
-  }
-  std::vector<int32_t> m((size_t)std::max(c->g.nx, c->g.nz));
-  for (int i = 0; i < c->g.nx; ++i) m[i] = i / c->tiles.tx;
-  HIP_TRY(c, hipMemcpy(c->col_tile, m.data(), (size_t)c->g.nx * sizeof(int32_t), hipMemcpyHostToDevice), "tile map");
-  for (int k = 0; k < c->g.nz; ++k) m[k] = k / c->tiles.tz;
-  HIP_TRY(c, hipMemcpy(c->row_tile, m.data(), (size_t)c->g.nz * sizeof(int32_t), hipMemcpyHostToDevice), "tile map");
   return PIC_OK;
 }
 
@@ -838,8 +827,6 @@ void pic_destroy(pic_ctx *c) {
     dfree(c, c->tlist[b], ((size_t)c->tiles_alloc + 1) * sizeof(int32_t));
   }
   dfree(c, c->mtile, (size_t)std::max(c->tiles_alloc, 1));
-  dfree(c, c->col_tile, (size_t)c->g.nx * sizeof(int32_t));
-  dfree(c, c->row_tile, (size_t)c->g.nz * sizeof(int32_t));
   for (auto &p : c->prof_ev)
     for (int q = 0; q < 4; ++q) (void)hipEventDestroy(p.ev[q]);
   if (c->own_stream) (void)hipStreamDestroy(c->own_stream);

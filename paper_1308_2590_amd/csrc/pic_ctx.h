@@ -52,7 +52,6 @@ struct pic_ctx {
   int32_t *tlist[2] = {};  // ordered active-tile lists, count at [ntiles]
   uint8_t *mtile = nullptr;  // deposit flags of the tiles (nodes whose moments can be nonzero)
   int32_t tiles_alloc = 0, tiles_tx = 0, tiles_tz = 0;
-  int32_t *col_tile = nullptr, *row_tile = nullptr;  // cell column / row -> tile index
   int64_t step = 0;
   int64_t bytes = 0;
   size_t lds_max = 65536;  // LDS a block may use on the context's device

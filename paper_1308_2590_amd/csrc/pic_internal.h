@@ -86,8 +86,6 @@ struct StepArgs {
   int32_t *tile_list_next;
   uint8_t *mtile;            // deposit flags set for every tile the fold reaches (may be NULL)
   int32_t n_scan1_blocks;   // blocks of kScan1Block cells in a cycle's sort scan
-  const int32_t *col_tile;   // [nx]: tile column of each cell column
-  const int32_t *row_tile;   // [nz]: tile row of each cell row
 };
 
 struct FieldArgs {

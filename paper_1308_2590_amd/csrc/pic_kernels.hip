@@ -1090,9 +1090,10 @@ __device__ __forceinline__ int64_t source_cell(const GridArgs &g, int iK, int kK
   return (int64_t)ks * g.nx + is;
 }
 
-// Whether the cell (is, ks) lies in a tile that held particles (its counts are valid).
-__device__ __forceinline__ bool cell_tile_active(const StepArgs &a, int is, int ks) {
-  return a.tile_active[a.row_tile[ks] * a.t.ntx + a.col_tile[is]] != 0;
+// Tile index of the cell (is, ks) (tiles are row-major, tx x tz cells; the last tile of a row
+// or column may be partial).
+__device__ __forceinline__ int cell_tile(const TileArgs &t, int is, int ks) {
+  return (ks / t.tz) * t.ntx + is / t.tx;
 }
 
 __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
@@ -1254,11 +1255,18 @@ __device__ __forceinline__ void rank_body(const StepArgs &a, int tile, int speci
       const int gk = wrap_any(k0 - 2 + rz, g.nz);
       bool in = true;
       if (g.bc_x == PIC_BC_PERIODIC) gi = wrap_any(gi, g.nx); else in = gi >= 0 && gi < g.nx;
-      const int64_t c = (int64_t)gk * g.nx + gi;
-      const bool act = in && cell_tile_active(a, gi, gk);
+      // The counts are valid only in tiles that held particles (the tile flag); they are
+      // loaded together with the flag (from a cell inside the grid) and kept or dropped after.
+      const int gic = min(max(gi, 0), g.nx - 1);
+      const int64_t c = (int64_t)gk * g.nx + gic;
+      const bool act = in && a.tile_active[cell_tile(t, gic, gk)] != 0;
+      int v[kMoveCodes];
 #pragma unroll
-      for (int d = 0; d < kMoveCodes; ++d) rcnt[d * RW * RH + e] = act ? sp.cnt[(int64_t)d * g.ncells + c] : 0;
-      rcsn[e] = in ? sp.cs_new[c] : 0;
+      for (int d = 0; d < kMoveCodes; ++d) v[d] = sp.cnt[(int64_t)d * g.ncells + c];
+      const int csn_c = sp.cs_new[c];
+#pragma unroll
+      for (int d = 0; d < kMoveCodes; ++d) rcnt[d * RW * RH + e] = act ? v[d] : 0;
+      rcsn[e] = in ? csn_c : 0;
     }
     __syncthreads();
     // (a tile without particles of this species has no counts: its table stays zero and its
@@ -1501,7 +1509,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_counts(const StepArgs a) {
     int k = (int)(c0 / g.nx), i = (int)(c0 - (int64_t)k * g.nx);
 #pragma unroll
     for (int q = 0; q < kScan1Items; ++q) {
-      if (in[q] && k < g.nz) a.tile_active_next[a.row_tile[k] * a.t.ntx + a.col_tile[i]] = 1;
+      if (in[q] && k < g.nz) a.tile_active_next[cell_tile(a.t, i, k)] = 1;
       if (++i == g.nx) {
         i = 0;
         ++k;
