@@ -501,15 +501,16 @@ __device__ __forceinline__ void drain_movers(const MoverQ<T> &q, int count, int 
 // halo (delta-j and density per node, S-hat scalars per corner of the tile's cells and their
 // one-cell ring), the fields the tile's particles read (E-bar on the tile's nodes, H^{n+1/2} on
 // its cells, H^{n+3/2} on its cells plus the ring), the per-wave mover queues, the int move
-// counters, and the arrival counts of the tile's cells and their ring.  Accumulators are FP64;
-// fields and queues use the kernel's arithmetic type.
+// counters, the arrival counts of the tile's cells and their ring, and the first and end slot
+// of every tile row of every species slot.  Accumulators are FP64; fields and queues use the
+// kernel's arithmetic type.
 struct TileLds {
   int LW, LH, plane;          // accumulator node grid (tx + 3) x (tz + 3)
   int EW, EPL;                // E-bar node grid (tx + 1) x (tz + 1)
   int HPL;                    // H^{n+1/2} cells tx x tz
   int NW, NPL;                // H^{n+3/2} cells (tx + 2) x (tz + 2)
   int n_node;                 // node accumulator planes: 3 + species
-  size_t acc, accc, eb, ho, hn, mq, cnt, arr;  // byte offsets
+  size_t acc, accc, eb, ho, hn, mq, cnt, arr, rows;  // byte offsets
   size_t bytes;
   __host__ __device__ TileLds(int n_planes, int tx, int tz, int tsize) {
     LW = tx + 3;
@@ -529,7 +530,8 @@ struct TileLds {
     mq = (hn + 3 * (size_t)NPL * tsize + 7) & ~(size_t)7;
     cnt = mq + (size_t)(kBlock / 64) * kMqCap * ((size_t)kMqWords * tsize + 2 * sizeof(int));
     arr = cnt + (size_t)tx * tz * 10 * sizeof(int);
-    bytes = arr + (size_t)(tx + 2) * (tz + 2) * sizeof(int);
+    rows = arr + (size_t)(tx + 2) * (tz + 2) * sizeof(int);
+    bytes = rows + (size_t)(n_node - 3) * tz * 2 * sizeof(int);
   }
 };
 
@@ -616,36 +618,81 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
   const int n_acc = Lo.n_node * plane + 12 * Lo.NPL;  // node planes, then cell-corner planes
 
   for (int e = threadIdx.x; e < n_acc; e += blockDim.x) acc.node[e] = 0.0;
-  // stage the fields of the tile
-  for (int e = threadIdx.x; e < Lo.HPL; e += blockDim.x) {
-    const int lk = e / t.tx, li = e - lk * t.tx;
-    const int gi = i0 + li, gk = k0 + lk;
-    const bool in = gi < g.nx && gk < g.nz;
-    const int64_t c = (int64_t)gk * g.nx + gi;
+  // Stage the fields of the tile and the slot range of every tile row of every species in one
+  // pass: a thread issues all its loads (at clamped, valid addresses) before it stores any, so
+  // the block waits for one memory round trip instead of one per array.
+  const int nrows_t = k1 - k0;
+  int *rowsL = reinterpret_cast<int *>(ldsb + Lo.rows);  // [species][row]: first, end slot
+  const int n_stage = max(max(Lo.HPL, nrows_t), PUSH ? max(Lo.EPL, Lo.NPL) : 0);
+  for (int e = threadIdx.x; e < n_stage; e += blockDim.x) {
+    // H^{n+1/2} on the tile's cells
+    const int eh = min(e, Lo.HPL - 1);
+    const int hk = eh / t.tx, hi = eh - hk * t.tx;
+    const bool h_in = e < Lo.HPL && i0 + hi < g.nx && k0 + hk < g.nz;
+    const int64_t ch = (int64_t)min(k0 + hk, g.nz - 1) * g.nx + min(i0 + hi, g.nx - 1);
+    double ho[3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) Ho[q * Lo.HPL + e] = in ? (T)a.Hold[q * nc + c] : T(0);
-  }
-  if (PUSH) {
-    for (int e = threadIdx.x; e < Lo.EPL; e += blockDim.x) {
-      const int lk = e / Lo.EW, li = e - lk * Lo.EW;
-      int gi = i0 + li;
-      const int gk = wrap_any(k0 + lk, g.nz);
-      bool in = true;
-      if (g.bc_x == PIC_BC_PERIODIC) gi = wrap_any(gi, g.nx); else in = gi <= g.nx;
-      const int64_t n = (int64_t)gk * g.nxn + gi;
+    for (int q = 0; q < 3; ++q) ho[q] = a.Hold[q * nc + ch];
+    // first and end slot of tile row e of every species (threads e < rows of the tile)
+    const bool r_th = e < nrows_t;
+    const int64_t rowc = (int64_t)(k0 + min(e, nrows_t - 1)) * g.nx;
+    int rbv[kMaxSpecies], rev[kMaxSpecies];
 #pragma unroll
-      for (int q = 0; q < 3; ++q)
-        Eb[q * Lo.EPL + e] = in ? (T)(0.5 * (a.Eold[q * nn + n] + a.Enew[q * nn + n])) : T(0);
+    for (int q = 0; q < kMaxSpecies; ++q) {
+      rbv[q] = 0;
+      rev[q] = 0;
+      if (q < a.nsp && a.sp[q].active && r_th) {
+        rbv[q] = a.sp[q].cs[rowc + i0];
+        rev[q] = a.sp[q].cs[rowc + i1];
+      }
     }
-    for (int e = threadIdx.x; e < Lo.NPL; e += blockDim.x) {
-      const int lk = e / Lo.NW, li = e - lk * Lo.NW;
-      int gi = i0 - 1 + li;
-      const int gk = wrap_any(k0 - 1 + lk, g.nz);
-      bool in = true;
-      if (g.bc_x == PIC_BC_PERIODIC) gi = wrap_any(gi, g.nx); else in = gi >= 0 && gi < g.nx;
-      const int64_t c = (int64_t)gk * g.nx + gi;
+    double eo[3], en[3], hn[3];
+    bool e_in = false, n_in = false;
+    if (PUSH) {
+      // E-bar on the tile's nodes
+      const int ee = min(e, Lo.EPL - 1);
+      const int ek = ee / Lo.EW, ei = ee - ek * Lo.EW;
+      int gi = i0 + ei;
+      const int gk = wrap_any(k0 + ek, g.nz);
+      e_in = e < Lo.EPL;
+      if (g.bc_x == PIC_BC_PERIODIC) gi = wrap_any(gi, g.nx); else e_in = e_in && gi <= g.nx;
+      const int64_t n = (int64_t)gk * g.nxn + min(gi, g.nxn - 1);
 #pragma unroll
-      for (int q = 0; q < 3; ++q) Hn[q * Lo.NPL + e] = in ? (T)a.Hnew[q * nc + c] : T(0);
+      for (int q = 0; q < 3; ++q) {
+        eo[q] = a.Eold[q * nn + n];
+        en[q] = a.Enew[q * nn + n];
+      }
+      // H^{n+3/2} on the tile's cells and their ring
+      const int en_ = min(e, Lo.NPL - 1);
+      const int nk = en_ / Lo.NW, ni = en_ - nk * Lo.NW;
+      int gi2 = i0 - 1 + ni;
+      const int gk2 = wrap_any(k0 - 1 + nk, g.nz);
+      n_in = e < Lo.NPL;
+      if (g.bc_x == PIC_BC_PERIODIC) gi2 = wrap_any(gi2, g.nx); else n_in = n_in && gi2 >= 0 && gi2 < g.nx;
+      const int64_t c2 = (int64_t)gk2 * g.nx + min(max(gi2, 0), g.nx - 1);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) hn[q] = a.Hnew[q * nc + c2];
+    }
+    if (e < Lo.HPL) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) Ho[q * Lo.HPL + e] = h_in ? (T)ho[q] : T(0);
+    }
+    if (r_th) {
+#pragma unroll
+      for (int q = 0; q < kMaxSpecies; ++q) {
+        if (q < a.nsp) {
+          rowsL[2 * (q * nrows_t + e)] = rbv[q];
+          rowsL[2 * (q * nrows_t + e) + 1] = rev[q];
+        }
+      }
+    }
+    if (PUSH && e < Lo.EPL) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) Eb[q * Lo.EPL + e] = e_in ? (T)(0.5 * (eo[q] + en[q])) : T(0);
+    }
+    if (PUSH && e < Lo.NPL) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) Hn[q * Lo.NPL + e] = n_in ? (T)hn[q] : T(0);
     }
   }
   __syncthreads();
@@ -677,8 +724,7 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
     const int wpr = nrows < nwaves ? nwaves / nrows : 1;
     const int part = wave % wpr;
     for (int r = k0 + wave / wpr; r < k1; r += nwaves / wpr) {
-      const int64_t rowc = (int64_t)r * g.nx;
-      const int rb = sp.cs[rowc + i0], re = sp.cs[rowc + i1];
+      const int rb = rowsL[2 * (s * nrows_t + (r - k0))], re = rowsL[2 * (s * nrows_t + (r - k0)) + 1];
       const int jb = rb + (int)((int64_t)(re - rb) * part / wpr);
       const int je = rb + (int)((int64_t)(re - rb) * (part + 1) / wpr);
       const int L = je - jb;
