@@ -1121,21 +1121,6 @@ void k_particles(const StepArgs a) {
 // Sort
 // ------------------------------------------------------------------------------------------
 
-// Source cell of destination cell (iK, kK) for move code d, or -1 if it does not exist; its
-// column and row are returned in is, ks.
-__device__ __forceinline__ int64_t source_cell(const GridArgs &g, int iK, int kK, int d, int &is,
-                                               int &ks) {
-  const int di = d % 3 - 1, dk = d / 3 - 1;
-  is = iK - di;
-  ks = wrap1(kK - dk, g.nz);
-  if (g.bc_x == PIC_BC_PERIODIC) {
-    is = wrap1(is, g.nx);
-  } else if (is < 0 || is >= g.nx) {
-    return -1;
-  }
-  return (int64_t)ks * g.nx + is;
-}
-
 // Tile index of the cell (is, ks) (tiles are row-major, tx x tz cells; the last tile of a row
 // or column may be partial).
 __device__ __forceinline__ int cell_tile(const TileArgs &t, int is, int ks) {
@@ -1225,31 +1210,6 @@ __device__ __forceinline__ void scan_finish_body(const StepArgs &a, int bx, int 
   }
 }
 
-// First slot, in the next order, of the particles moving from cell (ic, kc) with move code
-// d: start of the destination cell plus everything arriving there from source cells that
-// come earlier in the current (cell-sorted) order.  cntv(is, ks, d) gives the counts,
-// csn(iK, kK) the next order's cell starts.  Returns 0 for a destination outside an
-// absorbing x axis (no particle carries such a code).
-template <typename Cnt, typename Csn>
-__device__ int dest_base(const GridArgs &g, int ic, int kc, int d, Cnt cntv, Csn csn) {
-  const int di = d % 3 - 1, dk = d / 3 - 1;
-  int iK = ic + di;
-  const int kK = wrap1(kc + dk, g.nz);
-  if (g.bc_x == PIC_BC_PERIODIC) {
-    iK = wrap1(iK, g.nx);
-  } else if (iK < 0 || iK >= g.nx) {
-    return 0;
-  }
-  const int64_t key_c = (int64_t)kc * g.nx + ic;
-  int base = csn(iK, kK);
-  for (int d2 = 0; d2 < kMoveCodes; ++d2) {
-    int is, ks;
-    const int64_t src = source_cell(g, iK, kK, d2, is, ks);
-    if (src >= 0 && src < key_c) base += cntv(is, ks, d2);
-  }
-  return base;
-}
-
 // Stable destinations of one tile's particles.  The destination base of every (cell, move
 // code) of the tile is computed once into LDS; then one wavefront per tile row (or part of a
 // row) walks the row's slots in order, 64 at a time: particles with the same (cell, code) in a
@@ -1271,6 +1231,7 @@ __device__ __forceinline__ void rank_body(const StepArgs &a, int tile, int speci
   int *ctr = ldsi + ntc * 9 + nwaves * (t.tx + 1) + wave * (t.tx * 10);  // [tx][10] per wave
   int *rcnt = ldsi + ntc * 9 + nwaves * (t.tx + 1 + t.tx * 10);       // [9][ring_cells]
   int *rcsn = rcnt + kMoveCodes * ring_cells;                         // [ring_cells]
+  int *rkey = rcsn + ring_cells;                                      // [ring_cells]
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
   // one block per (tile, species): twice the blocks of a per-tile launch, to overlap the
@@ -1313,24 +1274,33 @@ __device__ __forceinline__ void rank_body(const StepArgs &a, int tile, int speci
 #pragma unroll
       for (int d = 0; d < kMoveCodes; ++d) rcnt[d * RW * RH + e] = act ? v[d] : 0;
       rcsn[e] = in ? csn_c : 0;
+      rkey[e] = in ? (int)c : -1;  // sort key of the cell; -1 outside an absorbing axis
     }
     __syncthreads();
     // (a tile without particles of this species has no counts: its table stays zero and its
     // rows are empty)
-    // local ring coordinates of a global cell near the tile (periodic wrap on both axes)
-    auto ring = [&](int gi, int gk) {
-      int rx = gi - (i0 - 2), rz = gk - (k0 - 2);
-      if (rx < 0) rx += g.nx; else if (rx >= RW) rx -= g.nx;
-      if (rz < 0) rz += g.nz; else if (rz >= RH) rz -= g.nz;
-      return rz * RW + rx;
-    };
-    auto cntv = [&](int is, int ks, int d) { return rcnt[d * RW * RH + ring(is, ks)]; };
-    auto csn = [&](int iK, int kK) { return rcsn[ring(iK, kK)]; };
     for (int e = threadIdx.x; e < ch * cw * kMoveCodes; e += blockDim.x) {
       const int cell = e / kMoveCodes, d = e - cell * kMoveCodes;
       const int lk = cell / cw, li = cell - lk * cw;
+      // First slot, in the next order, of the particles moving from this cell with code d:
+      // the start of the destination cell plus the particles arriving there from source
+      // cells earlier in the current (cell-sorted) order.  Destination and sources lie in
+      // the ring, so they are found by ring offsets; the order uses the cells' sort keys.
+      const int rc = (lk + 2) * RW + (li + 2);
       int b = 0;
-      if (rcnt[d * RW * RH + (lk + 2) * RW + (li + 2)] > 0) b = dest_base(g, i0 + li, k0 + lk, d, cntv, csn);
+      if (rcnt[d * RW * RH + rc] > 0) {
+        const int rd = rc + (d / 3 - 1) * RW + (d % 3 - 1);  // destination
+        if (rkey[rd] >= 0) {
+          const int key_c = rkey[rc];
+          b = rcsn[rd];
+#pragma unroll
+          for (int d2 = 0; d2 < kMoveCodes; ++d2) {
+            const int rs = rd - (d2 / 3 - 1) * RW - (d2 % 3 - 1);  // source sending d2 to rd
+            const int ks = rkey[rs];
+            if (ks >= 0 && ks < key_c) b += rcnt[d2 * RW * RH + rs];
+          }
+        }
+      }
       btab[(lk * t.tx + li) * kMoveCodes + d] = b;
     }
     __syncthreads();
@@ -1799,7 +1769,7 @@ size_t rank_lds_bytes(const TileArgs &t) {
   const int nw = kBlock / 64;
   const size_t ring = (size_t)(t.tx + 4) * (t.tz + 4);
   return ((size_t)t.tx * t.tz * kMoveCodes + (size_t)nw * ((t.tx + 1) + t.tx * 10) +
-          ring * (kMoveCodes + 1)) * sizeof(int);
+          ring * (kMoveCodes + 2)) * sizeof(int);
 }
 
 hipError_t launch_field_solve(const FieldArgs &a, hipStream_t s) {
