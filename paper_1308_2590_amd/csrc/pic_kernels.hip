@@ -339,6 +339,12 @@ __global__ __launch_bounds__(kBlock) void k_update_h(const FieldArgs a, int64_t 
 // Particles
 // ------------------------------------------------------------------------------------------
 
+// The value of the lane below (lane 0 gets its own): a DPP wave shift by one lane, which
+// stays in the VALU instead of the LDS crossbar.
+__device__ __forceinline__ int lane_before(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x138 /* wave_shr:1 */, 0xf, 0xf, false);
+}
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -1368,7 +1374,7 @@ __device__ __forceinline__ void rank_body(const StepArgs &a, int tile, int speci
               }
               cl = lo;
             }
-            clb = __shfl(cl, min(63, je - 1 - base), 64);  // cell of the group's last slot
+            clb = __builtin_amdgcn_readlane(cl, min(63, je - 1 - base));  // cell of the group's last slot
           }
           if (act) {
             const uint32_t lc = lcs[q];
@@ -1379,7 +1385,7 @@ __device__ __forceinline__ void rank_body(const StepArgs &a, int tile, int speci
           // The group's slots are in cell order, so the lanes of one cell are contiguous:
           // [cstart, cend).  A particle's rank within its (cell, code) in this group is the
           // number of lanes of its cell below it with the same code.
-          const int prevcl = __shfl_up(cl, 1, 64);
+          const int prevcl = lane_before(cl);
           const uint64_t heads = __ballot(act && (lane == 0 || prevcl != cl));
           const uint64_t upto = heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
           const int cstart = upto ? 63 - __clzll((long long)upto) : 0;
