@@ -345,6 +345,19 @@ __device__ __forceinline__ int lane_before(int v) {
   return __builtin_amdgcn_update_dpp(v, v, 0x138 /* wave_shr:1 */, 0xf, 0xf, false);
 }
 
+// The value of the lane above (lane 63 gets its own), by DPP wave shifts of 32-bit halves.
+__device__ __forceinline__ int lane_after(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x130 /* wave_shl:1 */, 0xf, 0xf, false);
+}
+__device__ __forceinline__ float lane_after(float v) {
+  return __int_as_float(lane_after(__float_as_int(v)));
+}
+__device__ __forceinline__ double lane_after(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = lane_after((int)(b & 0xffffffffll)), hi = lane_after((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -449,12 +462,31 @@ struct CellAcc {
   // atomics; same-address atomics from many lanes of one instruction are serialised.  All 64
   // lanes must be active.
   __device__ __forceinline__ void flush_row_end(const AccLds &acc, int lz, int dplane, int lane) {
-    const int prev = __shfl_up(cell, 1);
+    const int prev = lane_before(cell);
     const bool head = lane == 0 || prev != cell;
     const uint64_t heads = __ballot(head);
     const uint64_t above = heads & ~((2ull << lane) - 1ull);
     const int seg_end = above ? __ffsll((unsigned long long)above) - 1 : 64;
-    for (int d = 1; d < 64; d <<= 1) {
+    {
+      // first step (neighbour one lane up) by DPP; the wider steps go through the LDS crossbar
+      const bool take = lane + 1 < seg_end;
+      if (!__any(take)) {
+        if (head && cell >= 0) flush(acc, lz, dplane);
+        return;
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        T v;
+        v = lane_after(A0[c]); A0[c] += take ? v : T(0);
+        v = lane_after(A1[c]); A1[c] += take ? v : T(0);
+        v = lane_after(A2[c]); A2[c] += take ? v : T(0);
+        v = lane_after(J0[c]); J0[c] += take ? v : T(0);
+        v = lane_after(J1[c]); J1[c] += take ? v : T(0);
+        v = lane_after(J2[c]); J2[c] += take ? v : T(0);
+        v = lane_after(D[c]); D[c] += take ? v : T(0);
+      }
+    }
+    for (int d = 2; d < 64; d <<= 1) {
       const bool take = lane + d < seg_end;
       if (!__any(take)) break;
 #pragma unroll
