@@ -358,6 +358,21 @@ __device__ __forceinline__ double lane_after(double v) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// Stores of the particle kernel as raw buffer stores: a lane without a value passes an offset
+// past the buffer's range, which the hardware drops, so the store needs no branch.  Every array
+// gets the same range, 2^31 bytes (a species holds fewer than 2^28 particles).
+constexpr int kStoreDrop = (int)0xFFFFFF00u;
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t store_rsrc(void *p) {
+  return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)0x80000000u, 0x00020000);
+}
+__device__ __forceinline__ void store_or_drop(double *p, int i, bool on, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), store_rsrc(p), on ? i * 8 : kStoreDrop, 0, 0);
+}
+__device__ __forceinline__ void store_or_drop(uint32_t *p, int i, bool on, uint32_t v) {
+  __builtin_amdgcn_raw_buffer_store_b32(v, store_rsrc(p), on ? i * 4 : kStoreDrop, 0, 0);
+}
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -631,7 +646,7 @@ struct Pstate<true> {
 // MIXED selects the mixed-precision form: FP32 state, gather, push and per-lane partial sums,
 // added into FP64 LDS accumulators and the FP64 moment planes.  The FP64 form needs about 240
 // VGPRs (two waves per SIMD); the FP32 form fits three.
-template <bool PUSH, bool MIXED>
+template <bool PUSH, bool MIXED, bool IDS>
 __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
   using T = typename std::conditional<MIXED, float, double>::type;
   const GridArgs &g = a.g;
@@ -970,24 +985,34 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
                 ca.clear();
                 ca.cell = li;
               }
-              if (ok) {
-                const int loc = jb + it * 64 + lane;
-                if constexpr (MIXED) {
+              if constexpr (MIXED) {
+                if (ok) {
+                  const int loc = jb + it * 64 + lane;
                   sp.mdst_cell[loc] = k2 * g.nx + i2;
                   sp.mdst[0][loc] = xn;
                   sp.mdst[1][loc] = zn;
                   sp.mdst[2][loc] = n0;
                   sp.mdst[3][loc] = n1;
                   sp.mdst[4][loc] = n2;
-                } else {
-                  sp.dst[0][loc] = xn;
-                  sp.dst[1][loc] = zn;
-                  sp.dst[2][loc] = n0;
-                  sp.dst[3][loc] = n1;
-                  sp.dst[4][loc] = n2;
+                  sp.locode[j] = ((uint32_t)loc << 4) | code;
                 }
-                if (sp.dst_id) sp.dst_id[loc] = sp.src_id[p];
-                sp.locode[j] = ((uint32_t)loc << 4) | code;
+              } else {
+                // FP64: every lane issues the stores, without a branch (a lane without a
+                // particle passes an offset the hardware drops), so the compiler knows how many
+                // stores each particle issues and waits for the next particle's loads alone.
+                // (The mixed form measured no gain from this and keeps plain stores.)
+                const int loc = jb + it * 64 + lane;
+                store_or_drop(sp.dst[0], loc, ok, xn);
+                store_or_drop(sp.dst[1], loc, ok, zn);
+                store_or_drop(sp.dst[2], loc, ok, n0);
+                store_or_drop(sp.dst[3], loc, ok, n1);
+                store_or_drop(sp.dst[4], loc, ok, n2);
+                store_or_drop(sp.locode, j, ok, ((uint32_t)loc << 4) | code);
+              }
+              if (ok) {
+                // particle ids (tests only): a separate instantiation, so that its load, which
+                // is waited for at once, does not enter the wait counts of the kernel without ids
+                if (IDS && sp.dst_id) sp.dst_id[jb + it * 64 + lane] = sp.src_id[p];
                 atomicAdd(&cntL[hc * 10 + code], 1);
               }
               // stayers add to the lane's accumulator, movers go through the queue
@@ -1144,7 +1169,7 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
   }
 }
 
-template <bool PUSH, bool MIXED>
+template <bool PUSH, bool MIXED, bool IDS>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2 + MIXED, 2 + MIXED)))
 void k_particles(const StepArgs a) {
   // clear the next order's tile flags (set by the scan of this cycle's sort); the grid has a
@@ -1152,7 +1177,7 @@ void k_particles(const StepArgs a) {
   if (threadIdx.x == 0 && (int)blockIdx.x < a.t.ntiles) a.tile_active_next[blockIdx.x] = 0;
   const int tile = block_tile(a.t, a.tile_list);
   if (tile < 0) return;
-  particles_body<PUSH, MIXED>(a, tile);
+  particles_body<PUSH, MIXED, IDS>(a, tile);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1718,7 +1743,7 @@ void kb_particles(const BatchArgs b) {
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
     const int r = find_run(b.pre_tiles, b.nruns, w);
     const StepArgs &sa = run_step(b, r);
-    particles_body<true, MIXED>(sa, sa.tile_list[w - b.pre_tiles[r]]);
+    particles_body<true, MIXED, true>(sa, sa.tile_list[w - b.pre_tiles[r]]);
     __syncthreads();
   }
 }
@@ -1821,16 +1846,22 @@ hipError_t launch_field_solve(const FieldArgs &a, hipStream_t s) {
 hipError_t launch_particles(const StepArgs &a, bool push, hipStream_t s) {
   const size_t lds = particle_lds_bytes(a.g, a.t, a.mixed != 0);
   const dim3 grid(8u * (unsigned)a.t.per_xcd);
+  bool ids = false;
+  for (int q = 0; q < a.nsp; ++q) ids = ids || a.sp[q].dst_id != nullptr;
   if (a.mixed) {
-    if (push)
-      hipLaunchKernelGGL((k_particles<true, true>), grid, dim3(kBlock), lds, s, a);
+    if (push && ids)
+      hipLaunchKernelGGL((k_particles<true, true, true>), grid, dim3(kBlock), lds, s, a);
+    else if (push)
+      hipLaunchKernelGGL((k_particles<true, true, false>), grid, dim3(kBlock), lds, s, a);
     else
-      hipLaunchKernelGGL((k_particles<false, true>), grid, dim3(kBlock), lds, s, a);
+      hipLaunchKernelGGL((k_particles<false, true, false>), grid, dim3(kBlock), lds, s, a);
   } else {
-    if (push)
-      hipLaunchKernelGGL((k_particles<true, false>), grid, dim3(kBlock), lds, s, a);
+    if (push && ids)
+      hipLaunchKernelGGL((k_particles<true, false, true>), grid, dim3(kBlock), lds, s, a);
+    else if (push)
+      hipLaunchKernelGGL((k_particles<true, false, false>), grid, dim3(kBlock), lds, s, a);
     else
-      hipLaunchKernelGGL((k_particles<false, false>), grid, dim3(kBlock), lds, s, a);
+      hipLaunchKernelGGL((k_particles<false, false, false>), grid, dim3(kBlock), lds, s, a);
   }
   return hipGetLastError();
 }
