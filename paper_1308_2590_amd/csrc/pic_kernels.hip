@@ -644,8 +644,9 @@ struct Pstate<true> {
 // particle at iteration `it` of lane `l` is written to location row_start + 64 it + l, which
 // makes the stores (and next cycle's loads through the permutation) coalesced.
 // MIXED selects the mixed-precision form: FP32 state, gather, push and per-lane partial sums,
-// added into FP64 LDS accumulators and the FP64 moment planes.  The FP64 form needs about 240
-// VGPRs (two waves per SIMD); the FP32 form fits three.
+// added into FP64 LDS accumulators and the FP64 moment planes.  The FP64 form needs about 250
+// VGPRs (two waves per SIMD); the FP32 form fits three.  IDS adds the copy of particle ids
+// (tests only).
 template <bool PUSH, bool MIXED, bool IDS>
 __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
   using T = typename std::conditional<MIXED, float, double>::type;
