@@ -35,6 +35,7 @@ import pytest
 import picgen
 from oracle import OracleSim
 from tests.pic_checks import abs_deposit_scale
+from tests.test_gpu_parity import rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -215,6 +216,42 @@ def test_mixed_one_step(pic, wi, tile):
     compare_step(ctx, orc, wl, prev)
     assert ctx.get_info()["overflow_flags"] == 0
     ctx.close()
+
+
+@pytest.mark.parametrize("wi", [0, 1, 3])
+def test_mixed_without_labels_matches_labelled(pic, wi):
+    """The mixed kernel without particle labels (the instantiation the benchmark runs) against
+    the labelled one, whose cycle test_mixed_one_step checks against the oracle: two cycles
+    from the same state give the same fields, moments and sorted particles (up to the order of
+    the FP64 atomic sums)."""
+    wl = SMALL[wi]
+    _say(f"mixed without labels {wl.name}")
+    fields = picgen.random_fields(100 + wi, wl.grid)
+    res = []
+    for ids in (True, False):
+        ctx, _ = setup_both(pic, wl, fields=fields, tile=(8, 2), track_ids=ids)
+        ctx.step(2)
+        res.append((ctx.read_fields(), ctx.read_moments(),
+                    [ctx.read_particles(s, ids=False) for s in range(len(wl.species))]))
+        assert ctx.get_info()["overflow_flags"] == 0
+        ctx.close()
+    (El, Hl), Ml, Pl = res[0]
+    (Eu, Hu), Mu, Pu = res[1]
+    assert rel_err(Eu, El) <= 1e-9 and rel_err(Hu, Hl) <= 1e-9
+    for p in range(Ml.shape[0]):
+        assert np.max(np.abs(Mu[p] - Ml[p]), initial=0.0) <= 1e-9 * max(np.max(np.abs(Ml[p]), initial=0.0), 1e-300), p
+    nx = wl.grid.nx
+    for s in range(len(wl.species)):
+        gl, gu = Pl[s], Pu[s]
+        assert len(gl["xi_x"]) == len(gu["xi_x"])
+        kl = np.floor(gl["xi_z"]).astype(np.int64) * nx + np.floor(gl["xi_x"]).astype(np.int64)
+        ku = np.floor(gu["xi_z"]).astype(np.int64) * nx + np.floor(gu["xi_x"]).astype(np.int64)
+        if not np.array_equal(kl, ku):
+            pytest.skip(f"species {s}: a particle on a cell face took the other side")
+        for k in ("xi_x", "xi_z"):
+            assert np.max(np.abs(gu[k] - gl[k]), initial=0.0) <= 1e-5, k
+        for k in ("ux", "uy", "uz"):
+            assert np.max(np.abs(gu[k] - gl[k]) / (1.0 + np.abs(gl[k])), initial=0.0) <= 1e-5, k
 
 
 def test_mixed_laser_absorbing(pic):

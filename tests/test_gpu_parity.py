@@ -156,6 +156,24 @@ def test_steps_from_identical_state(pic, wi, tile):
     ctx.close()
 
 
+@pytest.mark.parametrize("wi", [0, 1, 3])
+def test_steps_without_labels(pic, wi):
+    """Three cycles without particle labels (the kernel instantiation the benchmark runs, which
+    has no label copy) against the oracle; the sorted orders are compared slot by slot."""
+    wl = SMALL[wi]
+    _say(f"steps without labels {wl.name}")
+    fields = picgen.random_fields(100 + wi, wl.grid, amp_e=0.05, amp_h=0.2)
+    ctx, orc = setup_both(pic, wl, fields=fields, tile=(8, 2), track_ids=False)
+    for _ in range(3):
+        ctx.step(1)
+        orc.step(1)
+        check_fields(ctx, orc)
+        check_moments(ctx, orc)
+        check_particles(ctx, orc, wl, ids=False)
+    assert ctx.get_info()["overflow_flags"] == 0
+    ctx.close()
+
+
 def test_laser_source_and_absorbing_boundary(pic):
     wl = picgen.random_small(42, nx=40, nz=12, ppc=2, bc_x=1, dx=0.3, dz=0.3, dt=0.2,
                              laser_a0=0.8)
