@@ -96,6 +96,10 @@ def parse():
     ap.add_argument("--mover-steps", type=int, default=1000,
                     help="cycles of the warm-plasma energy comparison of the mover options "
                          "(0 skips the mover-option section)")
+    ap.add_argument("--batch-runs", type=int, default=32,
+                    help="runs of the batched FP64 / mixed comparison (0 skips it)")
+    ap.add_argument("--batch-steps", type=int, default=50,
+                    help="timed cycles of the batched FP64 / mixed comparison")
     ap.add_argument("--serve-runs", type=int, default=256,
                     help="requests of the batched serving stream (0 skips it)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="request arrivals per second")
@@ -330,6 +334,45 @@ def mover_options(binding, torch, steps):
     return res
 
 
+def batched(binding, torch, nruns, steps, warmup):
+    """The batched form in both precisions: `nruns` independent foil runs of uneven size (drawn
+    like the serving stream: sides log-uniform in [32, 512], slab 5-15 % of x, density 10-200
+    n_c, 8-64 particles per cell) stepped together by the persistent batch kernels with graph
+    replay, first all in FP64, then all in mixed precision: aggregate particle-steps/s of each
+    (particles alive, averaged over the timed cycles) and the speedup of the mixed batch."""
+    reqs = picgen.serving_stream(nruns, seed=11)
+    res = {"runs": nruns, "cycles": steps, "graph": True}
+    for name, prec in (("fp64", picgen.PREC_FP64), ("mixed", picgen.PREC_MIXED)):
+        b = binding.Batch(0, prec)
+        ctxs = []
+        for r in reqs:
+            wl = picgen.request_workload(r, precision=prec)
+            ctx = binding.Context(wl.grid, precision=prec)
+            for s, sp in enumerate(wl.species):
+                ctx.load_particles(s, sp.q, sp.m, sp.w, sp.xi_x, sp.xi_z, sp.ux, sp.uy, sp.uz)
+            b.add(ctx)
+            ctxs.append(ctx)
+        b.set_graph(True)
+        b.step(warmup)
+        b.sync()
+        alive = lambda: sum(sum(c.get_info()["alive"]) for c in ctxs)
+        n0 = alive()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(steps)
+        b.sync()
+        dt = time.perf_counter() - t0
+        n1 = alive()
+        res[name] = {"particles": n0, "ms_per_step": dt / steps * 1e3,
+                     "particle_steps_per_s": 0.5 * (n0 + n1) * steps / dt}
+        b.close()
+        for c in ctxs:
+            c.close()
+    res["speedup_mixed_over_fp64"] = (res["mixed"]["particle_steps_per_s"]
+                                      / res["fp64"]["particle_steps_per_s"])
+    return res
+
+
 def serving(args):
     """The batched serving stream: independent foil runs arriving Poisson at serve_rate per
     second (grid sides log-uniform in [32, 512], slab 5-15 % of x, density 10-200 n_c,
@@ -424,6 +467,10 @@ def main():
     if args.mover_steps > 0:
         out["mover_options"] = mover_options(binding, torch, args.mover_steps)
         print("[bench] mover options done", file=sys.stderr, flush=True)
+    if args.batch_runs > 0:
+        out["batched_fp64_vs_mixed"] = batched(binding, torch, args.batch_runs, args.batch_steps,
+                                               args.warmup)
+        print("[bench] batched comparison done", file=sys.stderr, flush=True)
     if args.serve_runs > 0:
         out["serving"] = serving(args)
         print("[bench] serving done", file=sys.stderr, flush=True)
