@@ -103,8 +103,10 @@ pic_status rebuild(pic_batch *b) {
   std::vector<int64_t> ctr(n);
   std::vector<int32_t> pre(8 * (n + 1), 0);
   size_t lds_p = 0, lds_r = 0;
+  bool ids = false;
   for (size_t r = 0; r < n; ++r) {
     pic_ctx *c = b->runs[r];
+    ids = ids || c->d.track_ids != 0;
     for (int p = 0; p < 2; ++p) {
       steps[2 * r + p] = pic::cycle_step_args(c, p);
       fields[2 * r + p] = pic::cycle_field_args(c, p);
@@ -150,10 +152,11 @@ pic_status rebuild(pic_batch *b) {
   a.pre_rank = b->d_pre + 7 * stride;
   pic::BatchLaunch &l = b->launch;
   l.mixed = b->precision == PIC_PREC_MIXED;
+  l.ids = ids;
   l.lds_particles = lds_p;
   l.lds_rank = lds_r;
   int per_p = 1, per_r = 1;
-  BHIP(b, pic::batch_occupancy(l.mixed, lds_p, lds_r, &per_p, &per_r), "occupancy");
+  BHIP(b, pic::batch_occupancy(l.mixed, l.ids, lds_p, lds_r, &per_p, &per_r), "occupancy");
   l.grid_particles = std::max(1, per_p) * b->cus;
   l.grid_rank = std::max(1, per_r) * b->cus;
   l.grid_small = 8 * b->cus;

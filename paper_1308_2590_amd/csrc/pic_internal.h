@@ -131,6 +131,7 @@ struct BatchLaunch {
   int32_t grid_rank;         // persistent blocks of the rank kernel
   size_t lds_particles, lds_rank;
   bool mixed;
+  bool ids;                  // some run copies particle ids (the kernel instantiation with ids)
 };
 
 size_t particle_lds_bytes(const GridArgs &g, const TileArgs &t, bool mixed);
@@ -152,8 +153,8 @@ hipError_t launch_iota(int32_t *p, int64_t n, hipStream_t s);
 // One cycle of every run of a batch (field solve, particles, sort, counters).
 hipError_t launch_batch_cycle(const BatchArgs &b, const BatchLaunch &l, hipStream_t s);
 // Persistent blocks per CU of the batched particle and rank kernels at the given LDS sizes.
-hipError_t batch_occupancy(bool mixed, size_t lds_particles, size_t lds_rank, int *per_cu_particles,
-                           int *per_cu_rank);
+hipError_t batch_occupancy(bool mixed, bool ids, size_t lds_particles, size_t lds_rank,
+                           int *per_cu_particles, int *per_cu_rank);
 // Build the active-tile flags and list of the order described by sp[].cs (into
 // tile_active_next / tile_list_next).
 hipError_t launch_tile_list(const StepArgs &a, bool from_next_order, hipStream_t s);

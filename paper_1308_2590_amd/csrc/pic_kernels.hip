@@ -1737,14 +1737,14 @@ __global__ __launch_bounds__(1024) void kb_prefix(const BatchArgs b) {
   }
 }
 
-template <bool MIXED>
+template <bool MIXED, bool IDS>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2 + MIXED, 2 + MIXED)))
 void kb_particles(const BatchArgs b) {
   const int total = b.pre_tiles[b.nruns];
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
     const int r = find_run(b.pre_tiles, b.nruns, w);
     const StepArgs &sa = run_step(b, r);
-    particles_body<true, MIXED, true>(sa, sa.tile_list[w - b.pre_tiles[r]]);
+    particles_body<true, MIXED, IDS>(sa, sa.tile_list[w - b.pre_tiles[r]]);
     __syncthreads();
   }
 }
@@ -1889,10 +1889,15 @@ hipError_t launch_batch_cycle(const BatchArgs &b, const BatchLaunch &l, hipStrea
   hipLaunchKernelGGL(kb_solve_e, small, blk, 0, s, b);
   hipLaunchKernelGGL(kb_update_h, small, blk, 0, s, b);
   hipLaunchKernelGGL(kb_prefix, dim3(1), dim3(1024), 0, s, b);
-  if (l.mixed)
-    hipLaunchKernelGGL(kb_particles<true>, dim3((unsigned)l.grid_particles), blk, l.lds_particles, s, b);
+  const dim3 gp((unsigned)l.grid_particles);
+  if (l.mixed && l.ids)
+    hipLaunchKernelGGL((kb_particles<true, true>), gp, blk, l.lds_particles, s, b);
+  else if (l.mixed)
+    hipLaunchKernelGGL((kb_particles<true, false>), gp, blk, l.lds_particles, s, b);
+  else if (l.ids)
+    hipLaunchKernelGGL((kb_particles<false, true>), gp, blk, l.lds_particles, s, b);
   else
-    hipLaunchKernelGGL(kb_particles<false>, dim3((unsigned)l.grid_particles), blk, l.lds_particles, s, b);
+    hipLaunchKernelGGL((kb_particles<false, false>), gp, blk, l.lds_particles, s, b);
   hipLaunchKernelGGL(kb_scan_counts, small, blk, 0, s, b);
   hipLaunchKernelGGL(kb_scan_blocks, small, dim3(1024), 0, s, b);
   hipLaunchKernelGGL(kb_scan_finish, small, blk, 0, s, b);
@@ -1903,15 +1908,21 @@ hipError_t launch_batch_cycle(const BatchArgs &b, const BatchLaunch &l, hipStrea
   return hipGetLastError();
 }
 
-hipError_t batch_occupancy(bool mixed, size_t lds_particles, size_t lds_rank, int *per_cu_particles,
-                           int *per_cu_rank) {
+hipError_t batch_occupancy(bool mixed, bool ids, size_t lds_particles, size_t lds_rank,
+                           int *per_cu_particles, int *per_cu_rank) {
   hipError_t e;
-  if (mixed)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_particles, kb_particles<true>, kBlock,
-                                                     lds_particles);
+  if (mixed && ids)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_particles, kb_particles<true, true>,
+                                                     kBlock, lds_particles);
+  else if (mixed)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_particles, kb_particles<true, false>,
+                                                     kBlock, lds_particles);
+  else if (ids)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_particles, kb_particles<false, true>,
+                                                     kBlock, lds_particles);
   else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_particles, kb_particles<false>, kBlock,
-                                                     lds_particles);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_particles, kb_particles<false, false>,
+                                                     kBlock, lds_particles);
   if (e != hipSuccess) return e;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_rank, kb_rank, kBlock, lds_rank);
 }
