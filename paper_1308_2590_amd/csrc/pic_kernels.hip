@@ -1515,29 +1515,51 @@ __global__ __launch_bounds__(kBlock) void k_tile_flags(const StepArgs a, int fro
 // neighbouring tiles.
 __device__ __forceinline__ void tile_compact_body(const StepArgs &a) {
   __shared__ int sh[1024 / 64];
-  constexpr int kPer = 16;
+  // A pass takes 64 flags per thread (four 16-byte words; tb is a multiple of 64), counts them
+  // with popcounts (flags are 0 or 1), places them with one block scan and writes the active
+  // tiles in order.
+  constexpr int kPer = 64;
   const int ntiles = a.t.ntiles;
+  const uint8_t *flags = a.tile_active_next;
   int carry = 0;
   for (int pbase = 0; pbase < ntiles; pbase += (int)blockDim.x * kPer) {
     const int tb = pbase + (int)threadIdx.x * kPer;
-    uint8_t f[kPer];
-    int n = 0;
-    if (tb + kPer <= ntiles) {  // 16 flags in one load (tb is a multiple of 16)
-      const uint4 v = *reinterpret_cast<const uint4 *>(a.tile_active_next + tb);
-      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    uint32_t w[kPer / 4];
 #pragma unroll
-      for (int q = 0; q < kPer; ++q) f[q] = (uint8_t)(w[q >> 2] >> (8 * (q & 3)));
-    } else {
+    for (int h = 0; h < kPer / 16; ++h) {
+      const int w0 = tb + 16 * h;
+      if (w0 + 16 <= ntiles) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(flags + w0);
+        w[4 * h] = v.x;
+        w[4 * h + 1] = v.y;
+        w[4 * h + 2] = v.z;
+        w[4 * h + 3] = v.w;
+      } else {
 #pragma unroll
-      for (int q = 0; q < kPer; ++q) f[q] = (tb + q < ntiles) ? a.tile_active_next[tb + q] : (uint8_t)0;
+        for (int q = 0; q < 4; ++q) {
+          uint32_t x = 0u;
+          for (int b = 0; b < 4; ++b) {
+            const int t = w0 + 4 * q + b;
+            if (t < ntiles) x |= (uint32_t)flags[t] << (8 * b);
+          }
+          w[4 * h + q] = x;
+        }
+      }
     }
+    int n = 0;
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) n += f[q];
+    for (int q = 0; q < kPer / 4; ++q) n += __popc(w[q]);
     int total;
     int pos = carry + block_excl_scan(n, sh, &total);
 #pragma unroll
-    for (int q = 0; q < kPer; ++q)
-      if (f[q]) a.tile_list_next[pos++] = tb + q;
+    for (int q = 0; q < kPer / 4; ++q) {
+      uint32_t x = w[q];
+      while (x) {
+        const int bit = __ffs(x) - 1;  // the set bit is bit 0 of byte bit / 8
+        a.tile_list_next[pos++] = tb + 4 * q + (bit >> 3);
+        x &= x - 1u;
+      }
+    }
     carry += total;
   }
   if (threadIdx.x == 0) a.tile_list_next[ntiles] = carry;
