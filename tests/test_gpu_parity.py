@@ -3,25 +3,28 @@
 Tolerances: floating-point arrays agree to 1e-10 in max-norm relative error (per array; per
 moment plane, relative to that plane's largest oracle value), as required of the FP64 path.
 Integer results (the cell-sorted order, carried as particle labels, and the cell of every
-particle) must be identical.  A particle whose oracle position lies within 1e-9 of a cell
-face may legitimately land in the neighbouring cell when the fields differ in the last bits
-(the GPU sums the deposit in a different order); such particles are reported, and everything
-else must still match exactly.
+particle) must be identical.  A particle whose new position lies within FACE_EPS (1e-11 cell)
+of a face may legitimately land in the neighbouring cell when the fields differ in the last
+bits (the GPU sums the deposit in a different order); only such a particle may be out of place,
+every other particle must match slot by slot.  Positions of up to 2048 cells carry rounding of
+about 5e-13 cell, so a real face crossing is expected about once in 1e10 particle-cycles.
 """
 from __future__ import annotations
 
 import sys
+from dataclasses import replace
 
 import numpy as np
 import pytest
 
 import picgen
 from oracle import OracleSim
+from tests.order_match import align_sorted, cell_keys, near_face
 
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-10
-FACE_EPS = 1e-9
+FACE_EPS = 1e-11
 
 
 def _say(msg):
@@ -79,32 +82,44 @@ def check_moments(ctx, orc, tol=TOL):
 
 
 def check_particles(ctx, orc, wl, tol=TOL, ids=True):
-    """Cell-sorted order identical (labels), cells identical, values within tol."""
+    """Cell-sorted order identical slot by slot (and the labels, when carried), values within
+    tol; a particle may be out of place only if it sits within FACE_EPS of a face on both
+    sides.  Returns the number of such particles."""
     nx, nz = wl.grid.nx, wl.grid.nz
+    n_amb = 0
     for s in range(len(wl.species)):
         g = ctx.read_particles(s, ids=ids)
         o = orc.particles(s)
-        assert len(g["xi_x"]) == len(o["xi_x"]), f"species {s}: count {len(g['xi_x'])} vs {len(o['xi_x'])}"
-        kg = np.floor(g["xi_z"]).astype(np.int64) * nx + np.floor(g["xi_x"]).astype(np.int64)
-        ko = np.floor(o["xi_z"]).astype(np.int64) * nx + np.floor(o["xi_x"]).astype(np.int64)
         # the GPU order is sorted by cell
-        assert np.all(np.diff(kg) >= 0)
-        mism = np.nonzero(kg != ko)[0] if not ids else np.nonzero(g["id"] != o["id"])[0]
-        if mism.size:
-            fx = np.abs(o["xi_x"] - np.round(o["xi_x"]))
-            fz = np.abs(o["xi_z"] - np.round(o["xi_z"]))
-            near = (fx < FACE_EPS) | (fz < FACE_EPS)
-            n_amb = int(near.sum())
-            assert n_amb > 0, f"species {s}: {mism.size} order mismatches, none near a cell face"
-            pytest.skip(f"species {s}: {n_amb} particles within {FACE_EPS} of a face; order "
-                        "comparison ambiguous")
-        for k in ("xi_x", "xi_z"):
-            d = np.abs(g[k] - o[k])
-            span = nx if k == "xi_x" else nz
-            d = np.minimum(d, span - d)   # periodic wrap of a particle sitting on x = 0
-            assert float(np.max(d, initial=0.0)) <= tol * span, f"species {s} {k}"
-        for k in ("ux", "uy", "uz"):
-            assert rel_err(g[k], o[k]) <= tol, f"species {s} {k}: {rel_err(g[k], o[k]):.3e}"
+        assert np.all(np.diff(cell_keys(g, nx)) >= 0), f"species {s}: GPU order not sorted by cell"
+        scale = {k: max(float(np.max(np.abs(o[k]), initial=0.0)), 1e-300) for k in ("ux", "uy", "uz")}
+
+        def close(a, b):
+            ok = np.ones(a.size, dtype=bool)
+            for k, span in (("xi_x", nx), ("xi_z", nz)):
+                d = np.abs(g[k][a] - o[k][b])
+                d = np.minimum(d, span - d)   # periodic wrap of a particle sitting on x = 0
+                ok &= d <= tol * span
+            for k in ("ux", "uy", "uz"):
+                ok &= np.abs(g[k][a] - o[k][b]) <= tol * scale[k]
+            if ids:
+                ok &= g["id"][a] == o["id"][b]
+            return ok
+
+        jg, jo, eg, eo = align_sorted(g, o, nx, close)
+        bad_g = eg[~near_face(g, eg, FACE_EPS, nx)]
+        bad_o = eo[~near_face(o, eo, FACE_EPS, nx)]
+        assert bad_g.size == 0 and bad_o.size == 0, (
+            f"species {s}: {bad_g.size} GPU / {bad_o.size} oracle particles out of place or beyond "
+            f"tolerance and not on a face (GPU slots {bad_g[:5].tolist()}, oracle slots "
+            f"{bad_o[:5].tolist()}; {jg.size} matched of {len(g['xi_x'])} / {len(o['xi_x'])})")
+        if ids:
+            assert np.array_equal(np.sort(g["id"][eg]), np.sort(o["id"][eo])), \
+                f"species {s}: the particles out of place differ between the two sides"
+        n_amb += max(eg.size, eo.size)
+    if n_amb:
+        print(f"[gpu-case] {n_amb} particles on a face took the other side", flush=True)
+    return n_amb
 
 
 def small_workloads():
@@ -354,6 +369,27 @@ def test_field_dominated_full_size_one_cycle(pic):
     state and one whole cycle (fields, moments, sorted particles) against the oracle."""
     wl = picgen.named("lowdensity")
     _say(f"field-dominated full size {wl.n_particles} particles")
+    ctx, orc = setup_both(pic, wl, track_ids=False)
+    check_moments(ctx, orc)
+    ctx.step(1)
+    orc.step(1)
+    check_fields(ctx, orc)
+    check_moments(ctx, orc)
+    check_particles(ctx, orc, wl, ids=False)
+    assert ctx.get_info()["overflow_flags"] == 0
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["foil_cm", "foil_dense_cm"])
+def test_count_matched_foils_full_size_one_cycle(pic, name):
+    """The count-matched foils in FP64 at full size, in the launch configuration the benchmark
+    times (automatic tiles, no labels): the 80-cell slab at 100 n_c and 64 particles per cell and
+    species (5.24M particles), and the 160-cell slab at 200 n_c and 128 particles per cell and
+    species (21.0M particles, the workload of the FP64 / mixed comparison).  The deposit of the
+    loaded state and one whole cycle against the oracle."""
+    wl = picgen.named(name)
+    wl = replace(wl, grid=replace(wl.grid, precision=picgen.PREC_FP64))
+    _say(f"count-matched foil full size {wl.name}: {wl.n_particles} particles")
     ctx, orc = setup_both(pic, wl, track_ids=False)
     check_moments(ctx, orc)
     ctx.step(1)
