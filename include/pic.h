@@ -127,22 +127,28 @@ typedef struct {
   double step_ms;            /* whole cycles, first kernel start to last kernel end */
 } pic_profile;
 
-/* Create a context: validate the descriptor, allocate E, E-bar, H (two time levels) and
+/* Create a context: validate the descriptor, allocate E and H (two time levels each) and
  * the moment planes on the device, and set E = e0, H = h0, t = 0 (Sec. 3.2 (1), (3)).
  * Errors: PIC_ERR_ARG for an invalid descriptor, PIC_ERR_OOM, PIC_ERR_DEVICE.  On error
  * *out is NULL. */
 pic_status pic_init_grid(const pic_grid_desc *desc, pic_ctx **out);
 
-/* Place n particles of species s (Sec. 3.2 (2)): charge q, mass m, density carried per
- * particle w (the n_alpha of Sec. 2), positions x^{k+1/2} in cell units and momenta u^k.
+/* Place n particles of species s (Sec. 3.2 (2)): charge q, mass m, positions x^{k+1/2} in
+ * cell units and momenta u^k, each array n doubles.  Every particle carries its own density
+ * (the n_alpha of the current j_alpha = n_alpha q_alpha v_alpha, Sec. 2 Eqs. (2)-(3)): w[a]
+ * when w is not NULL, otherwise w_uniform for every particle of the species.  Per-particle
+ * densities travel with their particles through every cycle (8 more bytes read and written
+ * per particle and cycle in FP64, 4 in the mixed form, which stores them as FP32).
  * Replaces whatever species s held.  The particles are stably sorted by cell (input order
  * breaks ties), and the moments M^{k+1/2} of all species are deposited again.  When
  * track_ids is set, particle a gets label a.  Errors: PIC_ERR_ARG (s out of range, n < 0,
- * m <= 0, q or w not finite, NULL array with n > 0), PIC_ERR_RANGE (a position outside
- * [0, nx) x [0, nz) or a non-finite value), PIC_ERR_OOM.  At most 2^28 - 1 particles per species. */
-pic_status pic_load_particles(pic_ctx *ctx, int32_t species, double q, double m, double w,
-                              int64_t n, const double *xi_x, const double *xi_z,
-                              const double *ux, const double *uy, const double *uz);
+ * m <= 0, q or w_uniform not finite, NULL position or momentum array with n > 0),
+ * PIC_ERR_RANGE (a position outside [0, nx) x [0, nz), or a non-finite momentum or w[a]),
+ * PIC_ERR_OOM.  At most 2^28 - 1 particles per species. */
+pic_status pic_load_particles(pic_ctx *ctx, int32_t species, double q, double m, int64_t n,
+                              const double *xi_x, const double *xi_z, const double *ux,
+                              const double *uy, const double *uz, const double *w,
+                              double w_uniform);
 
 /* Replace E^k ([3][nodes]) and H^{k+1/2} ([3][cells]); either may be NULL to keep it.
  * The moments are deposited again since they depend on H at the particles.
@@ -174,9 +180,12 @@ pic_status pic_read_fields(pic_ctx *ctx, double *e, double *h);
 
 /* Copy species s in its current (cell-sorted) order.  *n_inout holds the capacity of the
  * arrays on entry and the particle count on return; PIC_ERR_ARG if the capacity is too
- * small (then *n_inout is the count needed).  id may be NULL; it needs track_ids. */
+ * small (then *n_inout is the count needed).  Any output array may be NULL.  w receives each
+ * particle's density (w_uniform for a species loaded without per-particle values); id needs
+ * track_ids. */
 pic_status pic_read_particles(pic_ctx *ctx, int32_t species, int64_t *n_inout, double *xi_x,
-                              double *xi_z, double *ux, double *uy, double *uz, int64_t *id);
+                              double *xi_z, double *ux, double *uy, double *uz, double *w,
+                              int64_t *id);
 
 /* Sizes, counters and device flags (waits for the stream). */
 pic_status pic_get_info(pic_ctx *ctx, pic_info *info);
@@ -213,7 +222,23 @@ pic_status pic_set_mover(pic_ctx *ctx, int32_t options);
  * PIC_ERR_ARG (out NULL or len too small). */
 pic_status pic_energy(pic_ctx *ctx, double *out, int32_t len);
 
-/* Message for the last failed call on this context (or of pic_init_grid when ctx is NULL). */
+/* Device memory.  By default a context (and a batch) allocates with hipMalloc and releases
+ * with hipFree.  pic_set_allocator installs a process-wide pair of functions used instead by
+ * every context and batch created after the call (each keeps the pair it was created with):
+ * alloc(bytes, device, user) returns device memory of at least bytes bytes on the given HIP
+ * device, aligned to 256 bytes, or NULL when it cannot; the library call then fails with
+ * PIC_ERR_OOM (pic_init_grid returns no context, pic_load_particles leaves the species
+ * without particles, pic_set_tiles keeps the old tiles).  free(ptr, bytes, device, user)
+ * releases a block with the size it was allocated with.  This is how a framework such as
+ * PyTorch lends the library its caching allocator.  The library frees memory only after the
+ * work queued on it has finished.  Passing NULL for both restores hipMalloc / hipFree.
+ * Errors: PIC_ERR_ARG if exactly one of alloc and free is NULL. */
+typedef void *(*pic_alloc_fn)(uint64_t bytes, int32_t device, void *user);
+typedef void (*pic_free_fn)(void *ptr, uint64_t bytes, int32_t device, void *user);
+pic_status pic_set_allocator(pic_alloc_fn alloc, pic_free_fn free_fn, void *user);
+
+/* Message for the last failed call on this context (or of pic_init_grid, pic_set_allocator
+ * or another call without a context when ctx is NULL). */
 const char *pic_last_error(const pic_ctx *ctx);
 
 /* Release the context and all its device memory (removing it from its batch first).  NULL is

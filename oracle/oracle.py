@@ -204,7 +204,7 @@ class OracleSim:
     def particles(self, s):
         sp = self.species[s]
         return {"xi_x": sp.xi_x.copy(), "xi_z": sp.xi_z.copy(), "ux": sp.ux.copy(),
-                "uy": sp.uy.copy(), "uz": sp.uz.copy(), "id": sp.id.copy()}
+                "uy": sp.uy.copy(), "uz": sp.uz.copy(), "w": sp.w.copy(), "id": sp.id.copy()}
 
     def gather(self, F, xi_x, xi_z):
         F = np.ascontiguousarray(F, dtype=np.float64)

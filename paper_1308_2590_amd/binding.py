@@ -25,7 +25,7 @@ EXPORTED = ["pic_init_grid", "pic_load_particles", "pic_load_fields", "pic_set_t
             "pic_set_step", "pic_step",
             "pic_read_moments", "pic_read_fields", "pic_read_particles", "pic_get_info",
             "pic_set_stream", "pic_sync", "pic_profile_enable", "pic_profile_read",
-            "pic_set_mover", "pic_energy",
+            "pic_set_mover", "pic_energy", "pic_set_allocator",
             "pic_last_error", "pic_destroy",
             "pic_batch_create", "pic_batch_add", "pic_batch_remove", "pic_batch_step",
             "pic_batch_set_graph", "pic_batch_sync", "pic_batch_size", "pic_batch_last_error",
@@ -67,6 +67,10 @@ class Profile(C.Structure):
                 ("step_ms", C.c_double)]
 
 
+# Device-memory hook types of pic_set_allocator.
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_uint64, C.c_int32, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_uint64, C.c_int32, C.c_void_p)
+
 _lib = None
 
 
@@ -86,14 +90,14 @@ def load_library(path: str = LIB_PATH):
     P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     sig = {
         "pic_init_grid": ([C.POINTER(GridDesc), C.POINTER(P)], C.c_int),
-        "pic_load_particles": ([P, I32, D, D, D, I64, P, P, P, P, P], C.c_int),
+        "pic_load_particles": ([P, I32, D, D, I64, P, P, P, P, P, P, D], C.c_int),
         "pic_load_fields": ([P, P, P], C.c_int),
         "pic_set_tiles": ([P, I32, I32], C.c_int),
         "pic_set_step": ([P, I64], C.c_int),
         "pic_step": ([P, I32], C.c_int),
         "pic_read_moments": ([P, P, I64], C.c_int),
         "pic_read_fields": ([P, P, P], C.c_int),
-        "pic_read_particles": ([P, I32, C.POINTER(I64), P, P, P, P, P, P], C.c_int),
+        "pic_read_particles": ([P, I32, C.POINTER(I64), P, P, P, P, P, P, P], C.c_int),
         "pic_get_info": ([P, C.POINTER(Info)], C.c_int),
         "pic_set_stream": ([P, P], C.c_int),
         "pic_sync": ([P], C.c_int),
@@ -101,6 +105,7 @@ def load_library(path: str = LIB_PATH):
         "pic_profile_read": ([P, C.POINTER(Profile)], C.c_int),
         "pic_set_mover": ([P, I32], C.c_int),
         "pic_energy": ([P, P, I32], C.c_int),
+        "pic_set_allocator": ([ALLOC_FN, FREE_FN, P], C.c_int),
         "pic_last_error": ([P], C.c_char_p),
         "pic_destroy": ([P], None),
         "pic_batch_create": ([I32, I32, C.POINTER(P)], C.c_int),
@@ -190,12 +195,19 @@ class Context:
 
     # -- the ABI --------------------------------------------------------------------------
     def load_particles(self, s, q, m, w, xi_x, xi_z, ux, uy, uz):
+        """w: one density for the whole species (a number) or one per particle (an array)."""
         arrs = [_f64(a) for a in (xi_x, xi_z, ux, uy, uz)]
         n = arrs[0].shape[0]
         if any(a.shape[0] != n for a in arrs):
             raise ValueError("particle arrays differ in length")
-        self._check(self.lib.pic_load_particles(self.h, int(s), float(q), float(m), float(w), n,
-                                                *[_p(a) for a in arrs]))
+        if np.ndim(w) == 0:
+            wa, wu = None, float(w)
+        else:
+            wa, wu = _f64(w), 0.0
+            if wa.shape[0] != n:
+                raise ValueError("w has another length than the particle arrays")
+        self._check(self.lib.pic_load_particles(self.h, int(s), float(q), float(m), n,
+                                                *[_p(a) for a in arrs], _p(wa), wu))
 
     def load_fields(self, e=None, h=None):
         e = None if e is None else _f64(e).reshape(-1)
@@ -242,11 +254,11 @@ class Context:
         info = self.get_info()
         n = int(info["alive"][s])
         cap = C.c_int64(n)
-        out = {k: np.empty(n) for k in ("xi_x", "xi_z", "ux", "uy", "uz")}
+        out = {k: np.empty(n) for k in ("xi_x", "xi_z", "ux", "uy", "uz", "w")}
         idv = np.empty(n, dtype=np.int64) if ids else None
         self._check(self.lib.pic_read_particles(self.h, int(s), C.byref(cap), _p(out["xi_x"]),
                                                 _p(out["xi_z"]), _p(out["ux"]), _p(out["uy"]),
-                                                _p(out["uz"]), _p(idv)))
+                                                _p(out["uz"]), _p(out["w"]), _p(idv)))
         if idv is not None:
             out["id"] = idv
         return out
@@ -337,3 +349,51 @@ class Batch:
 
 def init_grid(grid, **kw) -> Context:
     return Context(grid, **kw)
+
+
+# Every callback pair ever installed: contexts and batches keep calling the pair they were
+# created with after another one is installed, so none may be released.
+_hooks = []
+
+
+def set_allocator(alloc=None, free=None):
+    """pic_set_allocator with Python callables alloc(bytes, device) -> int address (0 when it
+    cannot) and free(address, bytes, device); None for both restores hipMalloc / hipFree.
+    Contexts and batches created afterwards use them."""
+    lib = load_library()
+    if (alloc is None) != (free is None):
+        raise ValueError("give both alloc and free, or neither")
+    if alloc is None:
+        st = lib.pic_set_allocator(C.cast(None, ALLOC_FN), C.cast(None, FREE_FN), None)
+        if st != PIC_OK:
+            raise PicError(st, lib.pic_last_error(None).decode())
+        return
+
+    def _a(nbytes, device, _user):
+        try:
+            return int(alloc(int(nbytes), int(device))) or None
+        except Exception:
+            return None
+
+    def _f(ptr, nbytes, device, _user):
+        free(int(ptr), int(nbytes), int(device))
+
+    hooks = (ALLOC_FN(_a), FREE_FN(_f))
+    _hooks.append(hooks)
+    st = lib.pic_set_allocator(hooks[0], hooks[1], None)
+    if st != PIC_OK:
+        raise PicError(st, lib.pic_last_error(None).decode())
+
+
+def use_torch_allocator():
+    """Back the library's device memory with PyTorch's caching allocator (on torch's current
+    stream of each device), so the library and torch share one pool."""
+    import torch
+
+    def alloc(nbytes, device):
+        return torch.cuda.caching_allocator_alloc(nbytes, device=device)
+
+    def free(ptr, nbytes, device):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    set_allocator(alloc, free)

@@ -91,14 +91,17 @@ __device__ double gamma_bar(const GridArgs &g, const double *En, int mover, doub
 
 // Deposit one particle's S-hat (9), delta-j (3) and density at its corner nodes: with
 // s = beta / gamma-bar and D = 1 + s^2 B.B, S-hat = (w q^2 dt^2 / (4 m gamma-bar D)) (I + s [B]x
-// + s^2 B B^T) and delta-j = (w q / (gamma-bar D)) (u + s u x B + s^2 (B.u) B).
+// + s^2 B B^T) and delta-j = (w q / (gamma-bar D)) (u + s u x B + s^2 (B.u) B), w the
+// particle's density (wp when the species carries one per particle).
 __device__ void deposit_one(const StepArgs &a, const SpeciesArgs &sp, int s, double gam,
                             const double u[3], const double B[3], const int64_t node[4],
-                            const double W[4]) {
+                            const double W[4], double wp) {
   const double sg = sp.beta / gam;
   const double inv = 1.0 / (1.0 + sg * sg * (B[0] * B[0] + B[1] * B[1] + B[2] * B[2]));
-  const double a0 = sp.cS / gam * inv, a1 = a0 * sg, a2 = a1 * sg;
-  const double kk = sp.kJ / gam * inv;
+  const double cS = sp.w_stride ? sp.cS1 * wp : sp.cS;
+  const double kJ = sp.w_stride ? sp.kJ1 * wp : sp.kJ;
+  const double a0 = cS / gam * inv, a1 = a0 * sg, a2 = a1 * sg;
+  const double kk = kJ / gam * inv;
   const double bu = B[0] * u[0] + B[1] * u[1] + B[2] * u[2];
   double v[13];
   v[0] = a2 * B[0] * B[0] + a0;
@@ -113,7 +116,7 @@ __device__ void deposit_one(const StepArgs &a, const SpeciesArgs &sp, int s, dou
   v[9] = kk * (u[0] + sg * (u[1] * B[2] - u[2] * B[1]) + sg * sg * bu * B[0]);
   v[10] = kk * (u[1] + sg * (u[2] * B[0] - u[0] * B[2]) + sg * sg * bu * B[1]);
   v[11] = kk * (u[2] + sg * (u[0] * B[1] - u[1] * B[0]) + sg * sg * bu * B[2]);
-  v[12] = sp.w;
+  v[12] = sp.w_stride ? wp : sp.w;
   const int64_t nn = a.g.nnodes;
   for (int c = 0; c < 4; ++c) {
     for (int r = 0; r < 12; ++r) unsafeAtomicAdd(&a.M[(int64_t)r * nn + node[c]], W[c] * v[r]);
@@ -140,6 +143,7 @@ __global__ __launch_bounds__(kBlock) void k_particles_alt(const StepArgs a, int 
   const int p = sp.perm[j];
   const double x = sp.src[0][p], z = sp.src[1][p];
   const double u[3] = {sp.src[2][p], sp.src[3][p], sp.src[4][p]};
+  const double wp = sp.w_stride ? sp.src_w[p] : sp.w;
   const int i = (int)floor(x), k = (int)floor(z);
   if (i < 0 || i >= g.nx || k < 0 || k >= g.nz) {
     atomicOr(a.flags, kFlagOrderA);
@@ -153,7 +157,7 @@ __global__ __launch_bounds__(kBlock) void k_particles_alt(const StepArgs a, int 
   b_at(g, a.Hold, mover, x, z, i, k, B);
   const double gam = gamma_bar(g, a.Eold, mover, sp.beta, u, node, W);
   if (!PUSH) {
-    deposit_one(a, sp, s, gam, u, B, node, W);
+    deposit_one(a, sp, s, gam, u, B, node, W, wp);
     return;
   }
   // E-bar at the particle and the implicit push: a = u + beta E-bar, b = beta B / gamma-bar,
@@ -205,6 +209,7 @@ __global__ __launch_bounds__(kBlock) void k_particles_alt(const StepArgs a, int 
   sp.dst[3][j] = un[1];
   sp.dst[4][j] = un[2];
   if (sp.dst_id) sp.dst_id[j] = sp.src_id[p];
+  if (sp.w_stride) sp.dst_w[j] = wp;
   sp.locode[j] = ((uint32_t)j << 4) | code;
   if (!alive) return;
   atomicAdd(&sp.cnt[(int64_t)code * g.ncells + (int64_t)k * g.nx + i], 1);
@@ -215,7 +220,7 @@ __global__ __launch_bounds__(kBlock) void k_particles_alt(const StepArgs a, int 
   corners(g, i2, k2, xn - (double)i2, zn - (double)k2, node2, W2);
   b_at(g, a.Hnew, mover, xn, zn, i2, k2, B2);
   const double gam2 = gamma_bar(g, a.Enew, mover, sp.beta, un, node2, W2);
-  deposit_one(a, sp, s, gam2, un, B2, node2, W2);
+  deposit_one(a, sp, s, gam2, un, B2, node2, W2, wp);
 }
 
 // Energies: out[0] field, out[1 + s] kinetic of species s (both times dx dz), summed over
@@ -261,10 +266,14 @@ __global__ __launch_bounds__(kBlock) void k_energy(const StepArgs a, const doubl
         u1 = sp.src[3][p];
         u2 = sp.src[4][p];
       }
-      kin += sqrt(1.0 + u0 * u0 + u1 * u1 + u2 * u2) - 1.0;
+      // the particle's density (one per species unless carried per particle)
+      double wp = 1.0;
+      if (sp.w_stride) wp = a.mixed ? (double)sp.msrc_w[p] : sp.src_w[p];
+      kin += wp * (sqrt(1.0 + u0 * u0 + u1 * u1 + u2 * u2) - 1.0);
     }
     const double ks = block_sum(kin, sh);
-    if (threadIdx.x == 0) unsafeAtomicAdd(&out[1 + s], ks * sp.w * sp.m * area);
+    const double wsp = sp.w_stride ? 1.0 : sp.w;
+    if (threadIdx.x == 0) unsafeAtomicAdd(&out[1 + s], ks * wsp * sp.m * area);
   }
 }
 

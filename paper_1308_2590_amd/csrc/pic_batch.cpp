@@ -32,6 +32,7 @@ struct pic_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   std::string err;
+  pic::DevAlloc mem;  // device memory of the tables (hipMalloc or the allocator hook)
 };
 
 namespace {
@@ -65,11 +66,11 @@ void drop_graph(pic_batch *b) {
 }
 
 void free_tables(pic_batch *b) {
-  (void)hipFree(b->d_step);
-  (void)hipFree(b->d_field);
-  (void)hipFree(b->d_par);
-  (void)hipFree(b->d_ctr);
-  (void)hipFree(b->d_pre);
+  b->mem.put(b->d_step);
+  b->mem.put(b->d_field);
+  b->mem.put(b->d_par);
+  b->mem.put(b->d_ctr);
+  b->mem.put(b->d_pre);
   b->d_step = nullptr;
   b->d_field = nullptr;
   b->d_par = nullptr;
@@ -82,11 +83,11 @@ pic_status grow(pic_batch *b, size_t n) {
   if (n <= b->cap) return PIC_OK;
   size_t cap = std::max<size_t>(n, 2 * b->cap);
   free_tables(b);
-  BHIP(b, hipMalloc(&b->d_step, 2 * cap * sizeof(pic::StepArgs)), "batch tables");
-  BHIP(b, hipMalloc(&b->d_field, 2 * cap * sizeof(pic::FieldArgs)), "batch tables");
-  BHIP(b, hipMalloc(&b->d_par, cap * sizeof(int32_t)), "batch tables");
-  BHIP(b, hipMalloc(&b->d_ctr, cap * sizeof(int64_t)), "batch tables");
-  BHIP(b, hipMalloc(&b->d_pre, 8 * (cap + 1) * sizeof(int32_t)), "batch tables");
+  BHIP(b, b->mem.get((void **)&b->d_step, 2 * cap * sizeof(pic::StepArgs)), "batch tables");
+  BHIP(b, b->mem.get((void **)&b->d_field, 2 * cap * sizeof(pic::FieldArgs)), "batch tables");
+  BHIP(b, b->mem.get((void **)&b->d_par, cap * sizeof(int32_t)), "batch tables");
+  BHIP(b, b->mem.get((void **)&b->d_ctr, cap * sizeof(int64_t)), "batch tables");
+  BHIP(b, b->mem.get((void **)&b->d_pre, 8 * (cap + 1) * sizeof(int32_t)), "batch tables");
   b->cap = cap;
   return PIC_OK;
 }
@@ -103,10 +104,14 @@ pic_status rebuild(pic_batch *b) {
   std::vector<int64_t> ctr(n);
   std::vector<int32_t> pre(8 * (n + 1), 0);
   size_t lds_p = 0, lds_r = 0;
-  bool ids = false;
+  bool ids = false, pw = false;
   for (size_t r = 0; r < n; ++r) {
     pic_ctx *c = b->runs[r];
     ids = ids || c->d.track_ids != 0;
+    for (int q = 0; q < c->S; ++q) pw = pw || (c->sp[q].loaded && c->sp[q].pw);
+  }
+  for (size_t r = 0; r < n; ++r) {
+    pic_ctx *c = b->runs[r];
     for (int p = 0; p < 2; ++p) {
       steps[2 * r + p] = pic::cycle_step_args(c, p);
       fields[2 * r + p] = pic::cycle_field_args(c, p);
@@ -122,7 +127,7 @@ pic_status rebuild(pic_batch *b) {
         (c->tiles.ntiles + pic::kBlock - 1) / pic::kBlock,
         1};
     for (int k = 0; k < 6; ++k) pre[k * (n + 1) + r + 1] = pre[k * (n + 1) + r] + items[k];
-    lds_p = std::max(lds_p, pic::particle_lds_bytes(c->g, c->tiles, b->precision == PIC_PREC_MIXED));
+    lds_p = std::max(lds_p, pic::particle_lds_bytes(c->g, c->tiles, b->precision == PIC_PREC_MIXED, pw));
     lds_r = std::max(lds_r, pic::rank_lds_bytes(c->tiles));
   }
   if (n > 0) {
@@ -153,10 +158,11 @@ pic_status rebuild(pic_batch *b) {
   pic::BatchLaunch &l = b->launch;
   l.mixed = b->precision == PIC_PREC_MIXED;
   l.ids = ids;
+  l.pw = pw;
   l.lds_particles = lds_p;
   l.lds_rank = lds_r;
   int per_p = 1, per_r = 1;
-  BHIP(b, pic::batch_occupancy(l.mixed, l.ids, lds_p, lds_r, &per_p, &per_r), "occupancy");
+  BHIP(b, pic::batch_occupancy(l.mixed, l.ids, l.pw, lds_p, lds_r, &per_p, &per_r), "occupancy");
   l.grid_particles = std::max(1, per_p) * b->cus;
   l.grid_rank = std::max(1, per_r) * b->cus;
   l.grid_small = 8 * b->cus;
@@ -209,6 +215,7 @@ pic_status pic_batch_create(int32_t device, int32_t precision, pic_batch **out) 
   pic_batch *b = new pic_batch();
   b->device = device;
   b->precision = precision;
+  b->mem = pic::current_allocator(device);
   hipDeviceProp_t prop;
   hipError_t e = hipGetDeviceProperties(&prop, device);
   if (e == hipSuccess) e = hipStreamCreate(&b->stream);

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -20,7 +21,63 @@ namespace {
 
 thread_local std::string g_init_error;
 
+// The allocator hook of pic_set_allocator (process-wide; each context and batch copies it when
+// it is created).
+std::mutex g_alloc_mu;
+pic_alloc_fn g_alloc = nullptr;
+pic_free_fn g_free = nullptr;
+void *g_alloc_user = nullptr;
+
 }  // namespace
+
+namespace pic {
+
+DevAlloc current_allocator(int32_t device) {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  DevAlloc a;
+  a.alloc = g_alloc;
+  a.free = g_free;
+  a.user = g_alloc_user;
+  a.device = device;
+  return a;
+}
+
+hipError_t DevAlloc::get(void **p, size_t n) {
+  *p = nullptr;
+  if (alloc) {
+    *p = alloc((uint64_t)n, device, user);
+    if (!*p) return hipErrorOutOfMemory;
+  } else {
+    const hipError_t e = hipMalloc(p, n);
+    if (e != hipSuccess) {
+      *p = nullptr;
+      return e;
+    }
+  }
+  live[*p] = n;
+  bytes += (int64_t)n;
+  return hipSuccess;
+}
+
+void DevAlloc::put(void *p) {
+  if (!p) return;
+  auto it = live.find(p);
+  const size_t n = it == live.end() ? 0 : it->second;
+  if (it != live.end()) live.erase(it);
+  bytes -= (int64_t)n;
+  if (free)
+    free(p, (uint64_t)n, device, user);
+  else
+    (void)hipFree(p);
+}
+
+void DevAlloc::put_all() {
+  std::vector<void *> ps;
+  for (auto &kv : live) ps.push_back(kv.first);
+  for (void *p : ps) put(p);
+}
+
+}  // namespace pic
 
 namespace {
 
@@ -48,19 +105,19 @@ pic_status dalloc(pic_ctx *c, T **p, size_t count, const char *what) {
   *p = nullptr;
   if (count == 0) count = 1;
   void *q = nullptr;
-  hipError_t e = hipMalloc(&q, count * sizeof(T));
-  if (e != hipSuccess) return hip_fail(c, e, what);
+  hipError_t e = c->mem.get(&q, count * sizeof(T));
+  if (e != hipSuccess) {
+    if (c->mem.alloc && e == hipErrorOutOfMemory)
+      return fail(c, PIC_ERR_OOM, std::string(what) + ": the allocator returned no memory for " +
+                                       std::to_string(count * sizeof(T)) + " bytes");
+    return hip_fail(c, e, what);
+  }
   *p = static_cast<T *>(q);
-  c->bytes += (int64_t)(count * sizeof(T));
   return PIC_OK;
 }
 
-void dfree(pic_ctx *c, void *p, size_t bytes) {
-  if (p) {
-    (void)hipFree(p);
-    c->bytes -= (int64_t)bytes;
-  }
-}
+// Release a block of the context (its size is known to the allocator record).
+void dfree(pic_ctx *c, void *p, size_t /*bytes*/) { c->mem.put(p); }
 
 void free_species(pic_ctx *c, SpeciesState &s) {
   const size_t cap = (size_t)std::max<int64_t>(s.cap, 1);
@@ -70,6 +127,8 @@ void free_species(pic_ctx *c, SpeciesState &s) {
     for (int v = 0; v < 5; ++v) dfree(c, s.mbuf[b][v], cap * sizeof(float)), s.mbuf[b][v] = nullptr;
     dfree(c, s.mcell[b], cap * sizeof(int32_t)), s.mcell[b] = nullptr;
     dfree(c, s.ids[b], cap * sizeof(int64_t)), s.ids[b] = nullptr;
+    dfree(c, s.wbuf[b], cap * sizeof(double)), s.wbuf[b] = nullptr;
+    dfree(c, s.mwbuf[b], cap * sizeof(float)), s.mwbuf[b] = nullptr;
     dfree(c, s.perm[b], (cap + pic::kPermPad) * sizeof(int32_t)), s.perm[b] = nullptr;
     dfree(c, s.cs[b], (nc + 1) * sizeof(int32_t)), s.cs[b] = nullptr;
   }
@@ -78,12 +137,20 @@ void free_species(pic_ctx *c, SpeciesState &s) {
   dfree(c, s.arr, nc * sizeof(int32_t)), s.arr = nullptr;
   dfree(c, s.bsum, (size_t)c->n_scan_blocks * sizeof(int32_t)), s.bsum = nullptr;
   s.loaded = false;
+  s.pw = false;
   s.cap = 0;
 }
 
 bool finite3(const double *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
 
 bool mixed(const pic_ctx *c) { return c->d.precision == PIC_PREC_MIXED; }
+
+// Whether some loaded species carries per-particle densities (the kernels with them run).
+bool any_pw(const pic_ctx *c) {
+  for (int s = 0; s < c->S; ++s)
+    if (c->sp[s].loaded && c->sp[s].pw) return true;
+  return false;
+}
 
 // Tile size from the load.  One wavefront handles one row of a tile, each lane a contiguous
 // run of that row's particles, so a tile is 4 rows high and wide enough for a row to hold
@@ -97,7 +164,8 @@ void choose_tiles(pic_ctx *c, int64_t total, int64_t occupied, int nspecies) {
     while (tx < 32 && (double)(2 * tx) * ppc <= 1024.0 * 1.4) tx *= 2;
     tz = 4;
     while (tx > 4 &&
-           pic::particle_lds_bytes(c->g, pic::TileArgs{tx, tz, 0, 0, 0, 0}, mixed(c)) > c->lds_max / 2)
+           pic::particle_lds_bytes(c->g, pic::TileArgs{tx, tz, 0, 0, 0, 0}, mixed(c), any_pw(c)) >
+               c->lds_max / 2)
       tx /= 2;
   }
   c->tiles.tx = tx;
@@ -129,6 +197,22 @@ pic::StepArgs step_args(pic_ctx *c, bool push) {
     x.beta = st.q * c->g.dt / (2.0 * st.m);
     x.cS = st.w * st.q * st.q * c->g.dt * c->g.dt / (4.0 * st.m);
     x.kJ = st.w * st.q;
+    x.cS1 = st.q * st.q * c->g.dt * c->g.dt / (4.0 * st.m);
+    x.kJ1 = st.q;
+    if (st.pw) {
+      x.w_stride = 1;
+      x.src_w = st.wbuf[cur];
+      x.dst_w = push ? st.wbuf[nxt] : nullptr;
+      x.msrc_w = st.mwbuf[cur];
+      x.mdst_w = push ? st.mwbuf[nxt] : nullptr;
+    } else {
+      // the species' single density, read with stride 0 and never written
+      x.w_stride = 0;
+      x.src_w = c->wconst64 + s;
+      x.dst_w = c->wconst64 + s;
+      x.msrc_w = c->wconst32 + s;
+      x.mdst_w = c->wconst32 + s;
+    }
     for (int v = 0; v < 5; ++v) {
       x.src[v] = st.buf[cur][v];
       x.dst[v] = push ? st.buf[nxt][v] : nullptr;
@@ -260,7 +344,7 @@ pic_status retile(pic_ctx *c) {
   int64_t occupied = 0;
   for (uint8_t o : occ) occupied += o;
   choose_tiles(c, total, occupied, nloaded);
-  if (pic::particle_lds_bytes(c->g, c->tiles, mixed(c)) > c->lds_max)
+  if (pic::particle_lds_bytes(c->g, c->tiles, mixed(c), any_pw(c)) > c->lds_max)
     return fail(c, PIC_ERR_ARG, "tile too large: its LDS accumulators exceed the LDS of a block");
   return PIC_OK;
 }
@@ -376,6 +460,7 @@ pic_status pic_init_grid(const pic_grid_desc *d, pic_ctx **out) {
 
   pic_ctx *c = new pic_ctx();
   c->d = *d;
+  c->mem = pic::current_allocator(d->device);
   c->lds_max = (size_t)lds_max;
   c->S = d->n_species;
   pic::GridArgs &g = c->g;
@@ -414,6 +499,11 @@ pic_status pic_init_grid(const pic_grid_desc *d, pic_ctx **out) {
   }
   if ((st = dalloc(c, &c->M, (size_t)g.n_planes * nn, "alloc moments")) != PIC_OK) return bail(st);
   if ((st = dalloc(c, &c->flags, 1, "alloc flags")) != PIC_OK) return bail(st);
+  // 8 doubles, then 8 floats
+  if ((st = dalloc(c, &c->wconst64, 12, "alloc densities")) != PIC_OK) return bail(st);
+  c->wconst32 = reinterpret_cast<float *>(c->wconst64 + PIC_MAX_SPECIES);
+  e = hipMemset(c->wconst64, 0, 12 * sizeof(double));
+  if (e != hipSuccess) return bail(hip_fail(c, e, "clear densities"));
   std::vector<double> host(3 * std::max(nn, nc));
   for (int r = 0; r < 3; ++r) std::fill(host.begin() + r * nn, host.begin() + (r + 1) * nn, d->e0[r]);
   e = hipMemcpy(c->E[0], host.data(), 3 * nn * sizeof(double), hipMemcpyHostToDevice);
@@ -429,14 +519,15 @@ pic_status pic_init_grid(const pic_grid_desc *d, pic_ctx **out) {
   return PIC_OK;
 }
 
-pic_status pic_load_particles(pic_ctx *c, int32_t s, double q, double m, double w, int64_t n,
+pic_status pic_load_particles(pic_ctx *c, int32_t s, double q, double m, int64_t n,
                               const double *xi_x, const double *xi_z, const double *ux,
-                              const double *uy, const double *uz) {
+                              const double *uy, const double *uz, const double *w,
+                              double w_uniform) {
   if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
   if (s < 0 || s >= c->S) return fail(c, PIC_ERR_ARG, "species index out of range");
   if (n < 0 || n >= (1LL << 28)) return fail(c, PIC_ERR_ARG, "n out of range (at most 2^28 - 1 per species)");
-  if (!std::isfinite(q) || !std::isfinite(w) || !(m > 0) || !std::isfinite(m))
-    return fail(c, PIC_ERR_ARG, "q, w must be finite and m positive");
+  if (!std::isfinite(q) || !std::isfinite(w_uniform) || !(m > 0) || !std::isfinite(m))
+    return fail(c, PIC_ERR_ARG, "q, w_uniform must be finite and m positive");
   if (n > 0 && (!xi_x || !xi_z || !ux || !uy || !uz)) return fail(c, PIC_ERR_ARG, "NULL particle array");
   const pic::GridArgs &g = c->g;
   const int64_t nc = g.ncells;
@@ -450,6 +541,8 @@ pic_status pic_load_particles(pic_ctx *c, int32_t s, double q, double m, double 
       return fail(c, PIC_ERR_RANGE, "particle " + std::to_string(a) + " lies outside the domain");
     if (!std::isfinite(ux[a]) || !std::isfinite(uy[a]) || !std::isfinite(uz[a]))
       return fail(c, PIC_ERR_RANGE, "particle " + std::to_string(a) + " has a non-finite momentum");
+    if (w && !std::isfinite(w[a]))
+      return fail(c, PIC_ERR_RANGE, "particle " + std::to_string(a) + " has a non-finite density");
     const int32_t i = (int32_t)std::floor(x), k = (int32_t)std::floor(z);
     key[a] = k * g.nx + i;
     start[(size_t)key[a] + 1] += 1;
@@ -464,46 +557,63 @@ pic_status pic_load_particles(pic_ctx *c, int32_t s, double q, double m, double 
   free_species(c, st);
   st.q = q;
   st.m = m;
-  st.w = w;
+  st.pw = w != nullptr;
+  // with per-particle densities the kernels scale unit-density moments by each particle's own
+  st.w = st.pw ? 1.0 : w_uniform;
   st.cap = n;
   st.n_loaded = n;
   const size_t cap = (size_t)std::max<int64_t>(n, 1);
+  // on any failure below the species is left without particles
+  auto bail = [&](pic_status r) {
+    const std::string msg = c->err;
+    free_species(c, st);
+    c->err = msg;
+    return r;
+  };
   pic_status rs;
   for (int b = 0; b < 2; ++b) {
     if (mixed(c)) {
-      if ((rs = dalloc(c, &st.mcell[b], cap, "alloc particles")) != PIC_OK) return rs;
+      if ((rs = dalloc(c, &st.mcell[b], cap, "alloc particles")) != PIC_OK) return bail(rs);
       for (int v = 0; v < 5; ++v)
-        if ((rs = dalloc(c, &st.mbuf[b][v], cap, "alloc particles")) != PIC_OK) return rs;
+        if ((rs = dalloc(c, &st.mbuf[b][v], cap, "alloc particles")) != PIC_OK) return bail(rs);
+      if (st.pw && (rs = dalloc(c, &st.mwbuf[b], cap, "alloc densities")) != PIC_OK) return bail(rs);
     } else {
       for (int v = 0; v < 5; ++v)
-        if ((rs = dalloc(c, &st.buf[b][v], cap, "alloc particles")) != PIC_OK) return rs;
+        if ((rs = dalloc(c, &st.buf[b][v], cap, "alloc particles")) != PIC_OK) return bail(rs);
+      if (st.pw && (rs = dalloc(c, &st.wbuf[b], cap, "alloc densities")) != PIC_OK) return bail(rs);
     }
     if (c->d.track_ids)
-      if ((rs = dalloc(c, &st.ids[b], cap, "alloc ids")) != PIC_OK) return rs;
+      if ((rs = dalloc(c, &st.ids[b], cap, "alloc ids")) != PIC_OK) return bail(rs);
     // padded: the particle kernel reads the permutation 4 entries at a time, up to 7 past
     // the last slot of a row part
-    if ((rs = dalloc(c, &st.perm[b], cap + pic::kPermPad, "alloc perm")) != PIC_OK) return rs;
-    HIP_TRY(c, hipMemset(st.perm[b], 0, (cap + pic::kPermPad) * sizeof(int32_t)), "clear perm");
-    if ((rs = dalloc(c, &st.cs[b], (size_t)nc + 1, "alloc cell starts")) != PIC_OK) return rs;
+    if ((rs = dalloc(c, &st.perm[b], cap + pic::kPermPad, "alloc perm")) != PIC_OK) return bail(rs);
+    if (hipMemset(st.perm[b], 0, (cap + pic::kPermPad) * sizeof(int32_t)) != hipSuccess)
+      return bail(fail(c, PIC_ERR_DEVICE, "clear perm"));
+    if ((rs = dalloc(c, &st.cs[b], (size_t)nc + 1, "alloc cell starts")) != PIC_OK) return bail(rs);
   }
-  if ((rs = dalloc(c, &st.locode, cap, "alloc codes")) != PIC_OK) return rs;
-  if ((rs = dalloc(c, &st.cnt, (size_t)pic::kMoveCodes * nc, "alloc counts")) != PIC_OK) return rs;
-  if ((rs = dalloc(c, &st.arr, (size_t)nc, "alloc arrivals")) != PIC_OK) return rs;
-  HIP_TRY(c, hipMemset(st.arr, 0, (size_t)nc * sizeof(int32_t)), "clear arrivals");
-  if ((rs = dalloc(c, &st.bsum, (size_t)c->n_scan_blocks, "alloc scan sums")) != PIC_OK) return rs;
+  if ((rs = dalloc(c, &st.locode, cap, "alloc codes")) != PIC_OK) return bail(rs);
+  if ((rs = dalloc(c, &st.cnt, (size_t)pic::kMoveCodes * nc, "alloc counts")) != PIC_OK) return bail(rs);
+  if ((rs = dalloc(c, &st.arr, (size_t)nc, "alloc arrivals")) != PIC_OK) return bail(rs);
+  if (hipMemset(st.arr, 0, (size_t)nc * sizeof(int32_t)) != hipSuccess)
+    return bail(fail(c, PIC_ERR_DEVICE, "clear arrivals"));
+  if ((rs = dalloc(c, &st.bsum, (size_t)c->n_scan_blocks, "alloc scan sums")) != PIC_OK) return bail(rs);
   {
+    auto up = [&](void *dst, const void *src, size_t bytes) {
+      const hipError_t e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+      return e == hipSuccess ? PIC_OK : hip_fail(c, e, "upload particles");
+    };
     const double *srcs[5] = {xi_x, xi_z, ux, uy, uz};
     if (mixed(c)) {
       // cell key and FP32 offsets in [0, 1) (an offset that rounds up to 1 is taken as the
-      // largest float below 1, so the particle stays in its cell), FP32 momenta
+      // largest float below 1, so the particle stays in its cell), FP32 momenta and densities
       std::vector<int32_t> kc((size_t)n);
       std::vector<float> tmp((size_t)n);
       for (int64_t j = 0; j < n; ++j) kc[j] = key[order[j]];
-      HIP_TRY(c, hipMemcpy(st.mcell[c->cur], kc.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice),
-              "upload particles");
-      for (int v = 0; v < 5; ++v) {
+      if ((rs = up(st.mcell[c->cur], kc.data(), (size_t)n * sizeof(int32_t))) != PIC_OK) return bail(rs);
+      for (int v = 0; v < 6; ++v) {
+        if (v == 5 && !st.pw) break;
         for (int64_t j = 0; j < n; ++j) {
-          const double x = srcs[v][order[j]];
+          const double x = v < 5 ? srcs[v][order[j]] : w[order[j]];
           if (v < 2) {
             float f = (float)(x - std::floor(x));
             if (f >= 1.0f) f = std::nextafter(1.0f, 0.0f);
@@ -512,27 +622,33 @@ pic_status pic_load_particles(pic_ctx *c, int32_t s, double q, double m, double 
             tmp[j] = (float)x;
           }
         }
-        HIP_TRY(c, hipMemcpy(st.mbuf[c->cur][v], tmp.data(), (size_t)n * sizeof(float), hipMemcpyHostToDevice),
-                "upload particles");
+        float *dst = v < 5 ? st.mbuf[c->cur][v] : st.mwbuf[c->cur];
+        if ((rs = up(dst, tmp.data(), (size_t)n * sizeof(float))) != PIC_OK) return bail(rs);
       }
     } else {
       std::vector<double> tmp((size_t)n);
-      for (int v = 0; v < 5; ++v) {
-        for (int64_t j = 0; j < n; ++j) tmp[j] = srcs[v][order[j]];
-        HIP_TRY(c, hipMemcpy(st.buf[c->cur][v], tmp.data(), (size_t)n * sizeof(double), hipMemcpyHostToDevice),
-                "upload particles");
+      for (int v = 0; v < 6; ++v) {
+        if (v == 5 && !st.pw) break;
+        for (int64_t j = 0; j < n; ++j) tmp[j] = v < 5 ? srcs[v][order[j]] : w[order[j]];
+        double *dst = v < 5 ? st.buf[c->cur][v] : st.wbuf[c->cur];
+        if ((rs = up(dst, tmp.data(), (size_t)n * sizeof(double))) != PIC_OK) return bail(rs);
       }
     }
     if (c->d.track_ids) {
       std::vector<int64_t> idv((size_t)n);
       for (int64_t j = 0; j < n; ++j) idv[j] = order[j];
-      HIP_TRY(c, hipMemcpy(st.ids[c->cur], idv.data(), (size_t)n * sizeof(int64_t), hipMemcpyHostToDevice),
-              "upload ids");
+      if ((rs = up(st.ids[c->cur], idv.data(), (size_t)n * sizeof(int64_t))) != PIC_OK) return bail(rs);
     }
+    // the species' single density, read with stride 0 by kernels with per-particle densities
+    const double wd = st.w;
+    const float wf = (float)st.w;
+    if ((rs = up(c->wconst64 + s, &wd, sizeof(double))) != PIC_OK) return bail(rs);
+    if ((rs = up(c->wconst32 + s, &wf, sizeof(float))) != PIC_OK) return bail(rs);
+    if ((rs = up(st.cs[c->cur], start.data(), ((size_t)nc + 1) * sizeof(int32_t))) != PIC_OK)
+      return bail(rs);
   }
-  HIP_TRY(c, hipMemcpy(st.cs[c->cur], start.data(), ((size_t)nc + 1) * sizeof(int32_t), hipMemcpyHostToDevice),
-          "upload cell starts");
-  HIP_TRY(c, pic::launch_iota(st.perm[c->cur], n, c->stream), "identity permutation");
+  if (pic::launch_iota(st.perm[c->cur], n, c->stream) != hipSuccess)
+    return bail(fail(c, PIC_ERR_DEVICE, "identity permutation"));
   st.loaded = true;
   {
     const pic_status rt = retile(c);
@@ -661,7 +777,7 @@ static pic_status alive_count(pic_ctx *c, int s, int64_t *n) {
 }
 
 pic_status pic_read_particles(pic_ctx *c, int32_t s, int64_t *n_inout, double *xi_x, double *xi_z,
-                              double *ux, double *uy, double *uz, int64_t *id) {
+                              double *ux, double *uy, double *uz, double *w, int64_t *id) {
   if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
   if (s < 0 || s >= c->S || !n_inout) return fail(c, PIC_ERR_ARG, "bad species or n_inout");
   if (id && !c->d.track_ids) return fail(c, PIC_ERR_ARG, "ids need track_ids");
@@ -707,6 +823,21 @@ pic_status pic_read_particles(pic_ctx *c, int32_t s, int64_t *n_inout, double *x
       for (int64_t j = 0; j < n; ++j) outs[v][j] = tmp[perm[j]];
     }
   }
+  if (w) {
+    if (!st.pw) {
+      std::fill(w, w + n, st.w);
+    } else if (mixed(c)) {
+      std::vector<float> tw((size_t)st.cap);
+      HIP_TRY(c, hipMemcpy(tw.data(), st.mwbuf[c->cur], (size_t)st.cap * sizeof(float), hipMemcpyDeviceToHost),
+              "read densities");
+      for (int64_t j = 0; j < n; ++j) w[j] = (double)tw[perm[j]];
+    } else {
+      std::vector<double> tw((size_t)st.cap);
+      HIP_TRY(c, hipMemcpy(tw.data(), st.wbuf[c->cur], (size_t)st.cap * sizeof(double), hipMemcpyDeviceToHost),
+              "read densities");
+      for (int64_t j = 0; j < n; ++j) w[j] = tw[perm[j]];
+    }
+  }
   if (id) {
     std::vector<int64_t> t2((size_t)st.cap);
     HIP_TRY(c, hipMemcpy(t2.data(), st.ids[c->cur], (size_t)st.cap * sizeof(int64_t), hipMemcpyDeviceToHost),
@@ -738,7 +869,7 @@ pic_status pic_get_info(pic_ctx *c, pic_info *info) {
     r.absorbed[s] = c->sp[s].loaded ? c->sp[s].n_loaded - n : 0;
   }
   HIP_TRY(c, hipMemcpy(&r.overflow_flags, c->flags, sizeof(uint32_t), hipMemcpyDeviceToHost), "read flags");
-  r.device_bytes = c->bytes;
+  r.device_bytes = c->mem.bytes;
   *info = r;
   return PIC_OK;
 }
@@ -808,6 +939,16 @@ pic_status pic_energy(pic_ctx *c, double *out, int32_t len) {
   return PIC_OK;
 }
 
+pic_status pic_set_allocator(pic_alloc_fn alloc, pic_free_fn free_fn, void *user) {
+  if ((alloc == nullptr) != (free_fn == nullptr))
+    return fail(nullptr, PIC_ERR_ARG, "alloc and free must both be given or both be NULL");
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_alloc = alloc;
+  g_free = free_fn;
+  g_alloc_user = alloc ? user : nullptr;
+  return PIC_OK;
+}
+
 const char *pic_last_error(const pic_ctx *c) { return c ? c->err.c_str() : g_init_error.c_str(); }
 
 void pic_destroy(pic_ctx *c) {
@@ -822,11 +963,13 @@ void pic_destroy(pic_ctx *c) {
   }
   dfree(c, c->M, (size_t)c->g.n_planes * nn * sizeof(double));
   dfree(c, c->flags, sizeof(uint32_t));
+  dfree(c, c->wconst64, 12 * sizeof(double));
   for (int b = 0; b < 2; ++b) {
     dfree(c, c->tact[b], (size_t)std::max(c->tiles_alloc, 1));
     dfree(c, c->tlist[b], ((size_t)c->tiles_alloc + 1) * sizeof(int32_t));
   }
   dfree(c, c->mtile, (size_t)std::max(c->tiles_alloc, 1));
+  c->mem.put_all();
   for (auto &p : c->prof_ev)
     for (int q = 0; q < 4; ++q) (void)hipEventDestroy(p.ev[q]);
   if (c->own_stream) (void)hipStreamDestroy(c->own_stream);

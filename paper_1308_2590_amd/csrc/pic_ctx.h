@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "pic.h"
@@ -12,8 +13,27 @@
 
 namespace pic {
 
+// Device memory of a context or batch: hipMalloc / hipFree, or the allocator hook installed by
+// pic_set_allocator when the context or batch was created.  Every block's size is recorded so
+// the hook's free gets the size it allocated.
+struct DevAlloc {
+  pic_alloc_fn alloc = nullptr;
+  pic_free_fn free = nullptr;
+  void *user = nullptr;
+  int32_t device = 0;
+  std::unordered_map<void *, size_t> live;
+  int64_t bytes = 0;
+  // hipErrorOutOfMemory when the hook returns NULL
+  hipError_t get(void **p, size_t bytes);
+  void put(void *p);
+  void put_all();
+};
+// The hook pair installed at this moment (empty for hipMalloc / hipFree).
+DevAlloc current_allocator(int32_t device);
+
 struct SpeciesState {
   bool loaded = false;
+  bool pw = false;         // per-particle densities (wbuf / mwbuf); otherwise w for all
   double q = 0, m = 1, w = 0;
   int64_t cap = 0;         // slots allocated
   int64_t n_loaded = 0;    // particles given at the last load
@@ -21,6 +41,8 @@ struct SpeciesState {
   int32_t *mcell[2] = {};  // mixed form: cell key k * nx + i
   float *mbuf[2][5] = {};  // mixed form: in-cell offsets f_x, f_z and u_x, u_y, u_z
   int64_t *ids[2] = {};
+  double *wbuf[2] = {};    // per-particle densities, FP64 form (addressed like buf)
+  float *mwbuf[2] = {};    // the same, mixed form (FP32)
   int32_t *perm[2] = {};
   int32_t *cs[2] = {};     // cell start offsets [ncells + 1]
   uint32_t *locode = nullptr;
@@ -48,12 +70,16 @@ struct pic_ctx {
   int ecur = 0, hcur = 0, cur = 0;  // flip together every cycle
   pic::SpeciesState sp[PIC_MAX_SPECIES];
   uint32_t *flags = nullptr;
+  // each species' single density (kernels with per-particle densities read it with stride 0
+  // for species loaded without per-particle values): FP64 at [0, 8), FP32 at wconst32
+  double *wconst64 = nullptr;
+  float *wconst32 = nullptr;
+  pic::DevAlloc mem;       // device memory of the context
   uint8_t *tact[2] = {};   // active-tile flags of the current / next order
   int32_t *tlist[2] = {};  // ordered active-tile lists, count at [ntiles]
   uint8_t *mtile = nullptr;  // deposit flags of the tiles (nodes whose moments can be nonzero)
   int32_t tiles_alloc = 0, tiles_tx = 0, tiles_tz = 0;
   int64_t step = 0;
-  int64_t bytes = 0;
   size_t lds_max = 65536;  // LDS a block may use on the context's device
   int32_t mover = 0;       // PIC_MOVER_* options; 0: the tile kernel's default mover
   int32_t n_scan_blocks = 0;

@@ -44,10 +44,18 @@ struct TileArgs {
 struct SpeciesArgs {
   double q, m, w;
   double beta;               // q dt / (2 m)
-  double cS;                 // w q^2 dt^2 / (4 m)
+  double cS;                 // w q^2 dt^2 / (4 m)  (uniform w)
   double kJ;                 // w q
+  double cS1, kJ1;           // q^2 dt^2 / (4 m) and q: per-particle densities multiply these
   const double *src[5];      // current state, addressed through perm (FP64 form)
   double *dst[5];            // pushed state, written in the kernel's processing order
+  // Per-particle densities (NULL for a species with one density w): FP64 form src_w / dst_w,
+  // mixed form msrc_w / mdst_w (FP32), addressed like the state arrays.
+  const double *src_w;
+  double *dst_w;
+  const float *msrc_w;
+  float *mdst_w;
+  int32_t w_stride;          // 1: per-particle densities; 0: src_w / msrc_w hold the single w
   const int32_t *msrc_cell;  // mixed form: cell key k * nx + i
   const float *msrc[5];      // mixed form: offsets f_x, f_z in [0, 1) and u_x, u_y, u_z
   int32_t *mdst_cell;
@@ -132,9 +140,12 @@ struct BatchLaunch {
   size_t lds_particles, lds_rank;
   bool mixed;
   bool ids;                  // some run copies particle ids (the kernel instantiation with ids)
+  bool pw;                   // some run carries per-particle densities
 };
 
-size_t particle_lds_bytes(const GridArgs &g, const TileArgs &t, bool mixed);
+// LDS of the particle kernel for a tile; pw: the instantiation with per-particle densities
+// (one more word per queued mover).
+size_t particle_lds_bytes(const GridArgs &g, const TileArgs &t, bool mixed, bool pw);
 size_t rank_lds_bytes(const TileArgs &t);
 
 hipError_t launch_field_solve(const FieldArgs &a, hipStream_t s);
@@ -153,7 +164,7 @@ hipError_t launch_iota(int32_t *p, int64_t n, hipStream_t s);
 // One cycle of every run of a batch (field solve, particles, sort, counters).
 hipError_t launch_batch_cycle(const BatchArgs &b, const BatchLaunch &l, hipStream_t s);
 // Persistent blocks per CU of the batched particle and rank kernels at the given LDS sizes.
-hipError_t batch_occupancy(bool mixed, bool ids, size_t lds_particles, size_t lds_rank,
+hipError_t batch_occupancy(bool mixed, bool ids, bool pw, size_t lds_particles, size_t lds_rank,
                            int *per_cu_particles, int *per_cu_rank);
 // Build the active-tile flags and list of the order described by sp[].cs (into
 // tile_active_next / tile_list_next).

@@ -414,6 +414,17 @@ __device__ __forceinline__ Compact<T> compact_moments(const SpConst<T> &k, T gin
   return m;
 }
 
+// The compact moments of unit density scaled to a particle's density w.
+template <typename T>
+__device__ __forceinline__ void scale_compact(Compact<T> &m, T w) {
+  m.a0 *= w;
+  m.a1 *= w;
+  m.a2 *= w;
+  m.j0 *= w;
+  m.j1 *= w;
+  m.j2 *= w;
+}
+
 // Add one corner's share of compact moments (one particle's, weighted, or a lane's sum):
 // delta-j and the density to the node planes at node o, and the three S-hat scalars to the
 // planes of that corner of cell rc.  S-hat is expanded with each cell's B only when the tile is
@@ -523,22 +534,24 @@ struct CellAcc {
 // Particles that change cell deposit into a different cell (and field) from the lane's run,
 // so they are queued per wavefront in LDS and deposited 64 at a time, one per lane.
 constexpr int kMqCap = 64;
-constexpr int kMqWords = 8;  // fx fz a0 a1 a2 j0 j1 j2
+// fx fz a0 a1 a2 j0 j1 j2, and the particle's density when densities are per particle
+__host__ __device__ constexpr int mq_words(bool pw) { return pw ? 9 : 8; }
 
 template <typename T>
 struct MoverQ {
-  T *v;      // [kMqWords][kMqCap]
+  T *v;      // [mq_words][kMqCap]
   int *idx;  // [2][kMqCap]: lower-left accumulator node, ring cell of the destination
 };
 
-template <typename T>
+template <typename T, bool PW>
 __device__ __forceinline__ void drain_movers(const MoverQ<T> &q, int count, int lane,
-                                             const AccLds &acc, int dplane, T w) {
+                                             const AccLds &acc, int dplane, T w_uniform) {
   if (lane < count) {
     const T fx = q.v[0 * kMqCap + lane], fz = q.v[1 * kMqCap + lane];
     const T a0 = q.v[2 * kMqCap + lane], a1 = q.v[3 * kMqCap + lane];
     const T a2 = q.v[4 * kMqCap + lane], j0 = q.v[5 * kMqCap + lane];
     const T j1 = q.v[6 * kMqCap + lane], j2 = q.v[7 * kMqCap + lane];
+    const T w = PW ? q.v[8 * kMqCap + lane] : w_uniform;
     const int o = q.idx[lane], rc = q.idx[kMqCap + lane];
 #pragma unroll 1
     for (int c = 0; c < 4; ++c) {
@@ -565,7 +578,7 @@ struct TileLds {
   int n_node;                 // node accumulator planes: 3 + species
   size_t acc, accc, eb, ho, hn, mq, cnt, arr, rows;  // byte offsets
   size_t bytes;
-  __host__ __device__ TileLds(int n_planes, int tx, int tz, int tsize) {
+  __host__ __device__ TileLds(int n_planes, int tx, int tz, int tsize, int qwords) {
     LW = tx + 3;
     LH = tz + 3;
     plane = LW * LH;
@@ -581,7 +594,7 @@ struct TileLds {
     ho = eb + 3 * (size_t)EPL * tsize;
     hn = ho + 3 * (size_t)HPL * tsize;
     mq = (hn + 3 * (size_t)NPL * tsize + 7) & ~(size_t)7;
-    cnt = mq + (size_t)(kBlock / 64) * kMqCap * ((size_t)kMqWords * tsize + 2 * sizeof(int));
+    cnt = mq + (size_t)(kBlock / 64) * kMqCap * ((size_t)qwords * tsize + 2 * sizeof(int));
     arr = cnt + (size_t)tx * tz * 10 * sizeof(int);
     rows = arr + (size_t)(tx + 2) * (tz + 2) * sizeof(int);
     bytes = rows + (size_t)(n_node - 3) * tz * 2 * sizeof(int);
@@ -646,8 +659,10 @@ struct Pstate<true> {
 // MIXED selects the mixed-precision form: FP32 state, gather, push and per-lane partial sums,
 // added into FP64 LDS accumulators and the FP64 moment planes.  The FP64 form needs about 250
 // VGPRs (two waves per SIMD); the FP32 form fits three.  IDS adds the copy of particle ids
-// (tests only).
-template <bool PUSH, bool MIXED, bool IDS>
+// (tests only).  PW selects per-particle densities: each particle's moments are those of unit
+// density times its own density, which is read with the state and written with the pushed
+// state (a species with one density reads it from a one-element array with stride 0).
+template <bool PUSH, bool MIXED, bool IDS, bool PW>
 __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
   using T = typename std::conditional<MIXED, float, double>::type;
   const GridArgs &g = a.g;
@@ -660,7 +675,8 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
 
   extern __shared__ double lds[];
   char *ldsb = reinterpret_cast<char *>(lds);
-  const TileLds Lo(g.n_planes, t.tx, t.tz, (int)sizeof(T));
+  constexpr int kQw = mq_words(PW);
+  const TileLds Lo(g.n_planes, t.tx, t.tz, (int)sizeof(T), kQw);
   const AccLds acc{reinterpret_cast<double *>(ldsb + Lo.acc),
                    reinterpret_cast<double *>(ldsb + Lo.accc), Lo.plane, Lo.NPL, Lo.LW, Lo.NW};
   T *Eb = reinterpret_cast<T *>(ldsb + Lo.eb);
@@ -755,9 +771,9 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   MoverQ<T> mq;
   {
-    char *qb = ldsb + Lo.mq + (size_t)wave * kMqCap * ((size_t)kMqWords * sizeof(T) + 2 * sizeof(int));
+    char *qb = ldsb + Lo.mq + (size_t)wave * kMqCap * ((size_t)kQw * sizeof(T) + 2 * sizeof(int));
     mq.v = reinterpret_cast<T *>(qb);
-    mq.idx = reinterpret_cast<int *>(qb + (size_t)kMqCap * kMqWords * sizeof(T));
+    mq.idx = reinterpret_cast<int *>(qb + (size_t)kMqCap * kQw * sizeof(T));
   }
   const T cxT = (T)g.cx, czT = (T)g.cz;
 
@@ -768,8 +784,19 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
       for (int e = threadIdx.x; e < ntc * 10; e += blockDim.x) cntL[e] = 0;
       __syncthreads();
     }
-    const SpConst<T> K{(T)sp.beta, (T)sp.cS, (T)sp.kJ, (T)sp.w};
+    const SpConst<T> K{(T)sp.beta, (T)(PW ? sp.cS1 : sp.cS), (T)(PW ? sp.kJ1 : sp.kJ), (T)sp.w};
     const typename Pstate<MIXED>::Src src(sp);
+    // per-particle densities: index p * wstride (stride 0 reads a species' single density)
+    const T *wsrc = nullptr;
+    T *wdst = nullptr;
+    if constexpr (MIXED) {
+      wsrc = sp.msrc_w;
+      wdst = sp.mdst_w;
+    } else {
+      wsrc = sp.src_w;
+      wdst = sp.dst_w;
+    }
+    const int wstride = sp.w_stride;
     const int32_t *perm = sp.perm;
     const int dplane = 3 + s;  // density plane of the species in the node accumulators
     // A tile with fewer rows than wavefronts splits each row's particles into wpr contiguous
@@ -807,6 +834,7 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
       constexpr int kChunk = 4;
       Pstate<MIXED> cb[kChunk];
       int cp_[kChunk], np_[kChunk];
+      T cw_[kChunk];
       // A chunk's permutation entries come in one 16-byte load per lane (the array is padded
       // so the load stays inside it); entries past the lane's run are clamped to a location
       // inside the state arrays and their particles go unused.
@@ -827,6 +855,7 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
         for (int kk = 0; kk < kChunk; ++kk) {
           cp_[kk] = np_[kk];
           cb[kk].load(src, cp_[kk]);
+          if constexpr (PW) cw_[kk] = wsrc[cp_[kk] * wstride];
         }
         perm4(start + c0 + kChunk, np_);
 #pragma unroll
@@ -851,6 +880,7 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
             fz = ps.z - (double)k;
           }
           const T u0 = ps.u0, u1 = ps.u1, u2 = ps.u2;
+          const T wp = PW ? cw_[kk] : K.w;  // the particle's density
           const bool ok = act && k == r && i >= i0 && i < i1;
           if (act && !ok) {
             atomicOr(a.flags, kFlagOrder);
@@ -883,13 +913,14 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
           const T one = T(1);
           const T ginv = rsqT(one + u0 * u0 + u1 * u1 + u2 * u2);  // 1 / gamma(u^n)
           if (!PUSH) {
-            const Compact<T> m0 = compact_moments(K, ginv, u0, u1, u2, fB0, fB1, fB2);
+            Compact<T> m0 = compact_moments(K, ginv, u0, u1, u2, fB0, fB1, fB2);
+            if constexpr (PW) scale_compact(m0, wp);
             if (newcell) {
               if (ca.cell >= 0) ca.flush(acc, lz, dplane);
               ca.clear();
               ca.cell = li;
             }
-            if (ok) ca.add(fx, fz, m0, K.w);
+            if (ok) ca.add(fx, fz, m0, wp);
           } else {
             bool mover = false;
             int mo = 0, mh = 0;
@@ -974,6 +1005,7 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
               // of the new cell (read before any LDS atomic of this particle is issued)
               const int hn = (lk + dk + 1) * Lo.NW + (li + di + 1);
               m = compact_moments(K, rg1, n0, n1, n2, Hn[hn], Hn[Lo.NPL + hn], Hn[2 * Lo.NPL + hn]);
+              if constexpr (PW) scale_compact(m, wp);
               if constexpr (MIXED) {
                 fx2 = xn;
                 fz2 = zn;
@@ -995,6 +1027,7 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
                   sp.mdst[2][loc] = n0;
                   sp.mdst[3][loc] = n1;
                   sp.mdst[4][loc] = n2;
+                  if (PW && wstride) wdst[loc] = wp;
                   sp.locode[j] = ((uint32_t)loc << 4) | code;
                 }
               } else {
@@ -1008,6 +1041,7 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
                 store_or_drop(sp.dst[2], loc, ok, n0);
                 store_or_drop(sp.dst[3], loc, ok, n1);
                 store_or_drop(sp.dst[4], loc, ok, n2);
+                if constexpr (PW) store_or_drop(wdst, loc, ok && wstride != 0, wp);
                 store_or_drop(sp.locode, j, ok, ((uint32_t)loc << 4) | code);
               }
               if (ok) {
@@ -1018,7 +1052,7 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
               }
               // stayers add to the lane's accumulator, movers go through the queue
               if (alive && code == 4u) {
-                ca.add(fx2, fz2, m, K.w);
+                ca.add(fx2, fz2, m, wp);
               } else if (alive) {
                 mover = true;
                 mo = (lz + dk) * LW + (li + 1 + di);
@@ -1030,7 +1064,7 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
             const int nm = __popcll(mmask);
             if (nq + nm > kMqCap) {
               wave_sync();
-              drain_movers(mq, nq, lane, acc, dplane, K.w);
+              drain_movers<T, PW>(mq, nq, lane, acc, dplane, K.w);
               wave_sync();
               nq = 0;
             }
@@ -1044,6 +1078,7 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
               mq.v[5 * kMqCap + e] = m.j0;
               mq.v[6 * kMqCap + e] = m.j1;
               mq.v[7 * kMqCap + e] = m.j2;
+              if constexpr (PW) mq.v[8 * kMqCap + e] = wp;
               mq.idx[e] = mo;
               mq.idx[kMqCap + e] = mh;
             }
@@ -1054,7 +1089,7 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
       ca.flush_row_end(acc, lz, dplane, lane);
       if (PUSH && nq > 0) {
         wave_sync();
-        drain_movers(mq, nq, lane, acc, dplane, K.w);
+        drain_movers<T, PW>(mq, nq, lane, acc, dplane, K.w);
         wave_sync();
       }
     }
@@ -1170,7 +1205,7 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
   }
 }
 
-template <bool PUSH, bool MIXED, bool IDS>
+template <bool PUSH, bool MIXED, bool IDS, bool PW>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2 + MIXED, 2 + MIXED)))
 void k_particles(const StepArgs a) {
   // clear the next order's tile flags (set by the scan of this cycle's sort); the grid has a
@@ -1178,7 +1213,7 @@ void k_particles(const StepArgs a) {
   if (threadIdx.x == 0 && (int)blockIdx.x < a.t.ntiles) a.tile_active_next[blockIdx.x] = 0;
   const int tile = block_tile(a.t, a.tile_list);
   if (tile < 0) return;
-  particles_body<PUSH, MIXED, IDS>(a, tile);
+  particles_body<PUSH, MIXED, IDS, PW>(a, tile);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1759,14 +1794,14 @@ __global__ __launch_bounds__(1024) void kb_prefix(const BatchArgs b) {
   }
 }
 
-template <bool MIXED, bool IDS>
+template <bool MIXED, bool IDS, bool PW>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2 + MIXED, 2 + MIXED)))
 void kb_particles(const BatchArgs b) {
   const int total = b.pre_tiles[b.nruns];
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
     const int r = find_run(b.pre_tiles, b.nruns, w);
     const StepArgs &sa = run_step(b, r);
-    particles_body<true, MIXED, IDS>(sa, sa.tile_list[w - b.pre_tiles[r]]);
+    particles_body<true, MIXED, IDS, PW>(sa, sa.tile_list[w - b.pre_tiles[r]]);
     __syncthreads();
   }
 }
@@ -1847,8 +1882,9 @@ __global__ void k_iota(int32_t *p, int64_t n) {
 
 }  // namespace
 
-size_t particle_lds_bytes(const GridArgs &g, const TileArgs &t, bool mixed) {
-  return TileLds(g.n_planes, t.tx, t.tz, mixed ? (int)sizeof(float) : (int)sizeof(double)).bytes;
+size_t particle_lds_bytes(const GridArgs &g, const TileArgs &t, bool mixed, bool pw) {
+  return TileLds(g.n_planes, t.tx, t.tz, mixed ? (int)sizeof(float) : (int)sizeof(double),
+                 mq_words(pw)).bytes;
 }
 
 size_t rank_lds_bytes(const TileArgs &t) {
@@ -1866,25 +1902,35 @@ hipError_t launch_field_solve(const FieldArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// The kernel instantiation for a cycle (push) or a deposit of the current state (no push):
+// precision, particle-id copy (push only) and per-particle densities.
+template <bool PUSH, bool MIXED>
+static void launch_particles_t(const StepArgs &a, bool ids, bool pw, dim3 grid, size_t lds,
+                               hipStream_t s) {
+  if (PUSH && ids && pw)
+    hipLaunchKernelGGL((k_particles<PUSH, MIXED, PUSH, true>), grid, dim3(kBlock), lds, s, a);
+  else if (PUSH && ids)
+    hipLaunchKernelGGL((k_particles<PUSH, MIXED, PUSH, false>), grid, dim3(kBlock), lds, s, a);
+  else if (pw)
+    hipLaunchKernelGGL((k_particles<PUSH, MIXED, false, true>), grid, dim3(kBlock), lds, s, a);
+  else
+    hipLaunchKernelGGL((k_particles<PUSH, MIXED, false, false>), grid, dim3(kBlock), lds, s, a);
+}
+
 hipError_t launch_particles(const StepArgs &a, bool push, hipStream_t s) {
-  const size_t lds = particle_lds_bytes(a.g, a.t, a.mixed != 0);
+  bool ids = false, pw = false;
+  for (int q = 0; q < a.nsp; ++q) {
+    ids = ids || a.sp[q].dst_id != nullptr;
+    pw = pw || (a.sp[q].active && a.sp[q].w_stride != 0);
+  }
+  const size_t lds = particle_lds_bytes(a.g, a.t, a.mixed != 0, pw);
   const dim3 grid(8u * (unsigned)a.t.per_xcd);
-  bool ids = false;
-  for (int q = 0; q < a.nsp; ++q) ids = ids || a.sp[q].dst_id != nullptr;
   if (a.mixed) {
-    if (push && ids)
-      hipLaunchKernelGGL((k_particles<true, true, true>), grid, dim3(kBlock), lds, s, a);
-    else if (push)
-      hipLaunchKernelGGL((k_particles<true, true, false>), grid, dim3(kBlock), lds, s, a);
-    else
-      hipLaunchKernelGGL((k_particles<false, true, false>), grid, dim3(kBlock), lds, s, a);
+    if (push) launch_particles_t<true, true>(a, ids, pw, grid, lds, s);
+    else launch_particles_t<false, true>(a, ids, pw, grid, lds, s);
   } else {
-    if (push && ids)
-      hipLaunchKernelGGL((k_particles<true, false, true>), grid, dim3(kBlock), lds, s, a);
-    else if (push)
-      hipLaunchKernelGGL((k_particles<true, false, false>), grid, dim3(kBlock), lds, s, a);
-    else
-      hipLaunchKernelGGL((k_particles<false, false, false>), grid, dim3(kBlock), lds, s, a);
+    if (push) launch_particles_t<true, false>(a, ids, pw, grid, lds, s);
+    else launch_particles_t<false, false>(a, ids, pw, grid, lds, s);
   }
   return hipGetLastError();
 }
@@ -1906,20 +1952,25 @@ hipError_t launch_tile_list(const StepArgs &a, bool from_next_order, hipStream_t
   return hipGetLastError();
 }
 
+typedef void (*BatchParticlesKernel)(BatchArgs);
+
+// The batched particle kernel instantiation: precision, particle-id copy, per-particle densities.
+static BatchParticlesKernel batch_particles_kernel(bool mixed, bool ids, bool pw) {
+  if (mixed) {
+    if (ids) return pw ? kb_particles<true, true, true> : kb_particles<true, true, false>;
+    return pw ? kb_particles<true, false, true> : kb_particles<true, false, false>;
+  }
+  if (ids) return pw ? kb_particles<false, true, true> : kb_particles<false, true, false>;
+  return pw ? kb_particles<false, false, true> : kb_particles<false, false, false>;
+}
+
 hipError_t launch_batch_cycle(const BatchArgs &b, const BatchLaunch &l, hipStream_t s) {
   const dim3 blk(kBlock), small((unsigned)l.grid_small);
   hipLaunchKernelGGL(kb_solve_e, small, blk, 0, s, b);
   hipLaunchKernelGGL(kb_update_h, small, blk, 0, s, b);
   hipLaunchKernelGGL(kb_prefix, dim3(1), dim3(1024), 0, s, b);
   const dim3 gp((unsigned)l.grid_particles);
-  if (l.mixed && l.ids)
-    hipLaunchKernelGGL((kb_particles<true, true>), gp, blk, l.lds_particles, s, b);
-  else if (l.mixed)
-    hipLaunchKernelGGL((kb_particles<true, false>), gp, blk, l.lds_particles, s, b);
-  else if (l.ids)
-    hipLaunchKernelGGL((kb_particles<false, true>), gp, blk, l.lds_particles, s, b);
-  else
-    hipLaunchKernelGGL((kb_particles<false, false>), gp, blk, l.lds_particles, s, b);
+  hipLaunchKernelGGL(batch_particles_kernel(l.mixed, l.ids, l.pw), gp, blk, l.lds_particles, s, b);
   hipLaunchKernelGGL(kb_scan_counts, small, blk, 0, s, b);
   hipLaunchKernelGGL(kb_scan_blocks, small, dim3(1024), 0, s, b);
   hipLaunchKernelGGL(kb_scan_finish, small, blk, 0, s, b);
@@ -1930,21 +1981,10 @@ hipError_t launch_batch_cycle(const BatchArgs &b, const BatchLaunch &l, hipStrea
   return hipGetLastError();
 }
 
-hipError_t batch_occupancy(bool mixed, bool ids, size_t lds_particles, size_t lds_rank,
+hipError_t batch_occupancy(bool mixed, bool ids, bool pw, size_t lds_particles, size_t lds_rank,
                            int *per_cu_particles, int *per_cu_rank) {
-  hipError_t e;
-  if (mixed && ids)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_particles, kb_particles<true, true>,
-                                                     kBlock, lds_particles);
-  else if (mixed)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_particles, kb_particles<true, false>,
-                                                     kBlock, lds_particles);
-  else if (ids)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_particles, kb_particles<false, true>,
-                                                     kBlock, lds_particles);
-  else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_particles, kb_particles<false, false>,
-                                                     kBlock, lds_particles);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      per_cu_particles, batch_particles_kernel(mixed, ids, pw), kBlock, lds_particles);
   if (e != hipSuccess) return e;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_rank, kb_rank, kBlock, lds_rank);
 }

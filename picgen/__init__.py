@@ -75,7 +75,7 @@ class Grid:
 class Species:
     q: float
     m: float
-    w: float  # density carried by each macro-particle (uniform within a species)
+    w: object  # density carried by each macro-particle: one number, or one per particle
     xi_x: np.ndarray
     xi_z: np.ndarray
     ux: np.ndarray
@@ -87,7 +87,8 @@ class Species:
         return int(self.xi_x.shape[0])
 
     def copy(self) -> "Species":
-        return replace(self, xi_x=self.xi_x.copy(), xi_z=self.xi_z.copy(),
+        w = self.w.copy() if isinstance(self.w, np.ndarray) else self.w
+        return replace(self, w=w, xi_x=self.xi_x.copy(), xi_z=self.xi_z.copy(),
                        ux=self.ux.copy(), uy=self.uy.copy(), uz=self.uz.copy())
 
 
@@ -281,6 +282,18 @@ def random_fields(seed, grid: Grid, amp_e=0.1, amp_h=0.3):
     return np.ascontiguousarray(e), np.ascontiguousarray(h)
 
 
+def with_particle_densities(wl: Workload, seed: int, spread=(0.2, 2.0)) -> Workload:
+    """Copy of a workload in which every particle carries its own density: the species'
+    density times a factor drawn uniformly from ``spread`` (seeded)."""
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + 13 * seed + 7))
+    out = []
+    for sp in wl.species:
+        c = sp.copy()
+        c.w = float(np.mean(sp.w)) * rng.uniform(spread[0], spread[1], sp.n)
+        out.append(c)
+    return replace(wl, species=out, name=wl.name + "_pw")
+
+
 def fp32_representable(wl: Workload) -> Workload:
     """Copy of a workload whose particle state is exactly representable in the mixed form:
     in-cell offsets and momenta rounded to the nearest float32 (an offset that rounds up to 1
@@ -296,6 +309,8 @@ def fp32_representable(wl: Workload) -> Workload:
             setattr(c, k, i + f.astype(np.float64))
         for k in ("ux", "uy", "uz"):
             setattr(c, k, getattr(c, k).astype(np.float32).astype(np.float64))
+        if isinstance(c.w, np.ndarray):   # per-particle densities are stored as FP32 too
+            c.w = c.w.astype(np.float32).astype(np.float64)
         out.append(c)
     return replace(wl, species=out, grid=replace(wl.grid, precision=PREC_MIXED))
 

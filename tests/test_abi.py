@@ -115,3 +115,20 @@ def test_batch_argument_errors_without_device():
     assert lib.pic_batch_size(None, C.byref(n)) == 1
     assert lib.pic_batch_set_graph(None, 1) == 1
     lib.pic_batch_destroy(None)
+
+
+def test_set_allocator_rejects_half_a_pair_without_device():
+    """pic_set_allocator takes both functions or neither; it touches no device."""
+    lib = binding.load_library()
+    null_a = C.cast(None, binding.ALLOC_FN)
+    null_f = C.cast(None, binding.FREE_FN)
+    hook = binding.ALLOC_FN(lambda n, d, u: None)
+    assert lib.pic_set_allocator(hook, null_f, None) == 1
+    assert b"both" in lib.pic_last_error(None)
+    assert lib.pic_set_allocator(null_a, null_f, None) == 0
+
+
+def test_load_particles_argument_errors_without_device():
+    """pic_load_particles refuses a NULL context before touching a device."""
+    lib = binding.load_library()
+    assert lib.pic_load_particles(None, 0, -1.0, 1.0, 0, None, None, None, None, None, None, 1.0) == 1

@@ -76,7 +76,7 @@ def compare(a, b, nsp, tol):
     for s in range(nsp):
         pa, pb = a.read_particles(s, ids=True), b.read_particles(s, ids=True)
         assert np.array_equal(pa["id"], pb["id"]), f"species {s}: order differs"
-        for k in ("xi_x", "xi_z", "ux", "uy", "uz"):
+        for k in ("xi_x", "xi_z", "ux", "uy", "uz", "w"):
             assert rel(pa[k], pb[k]) <= tol, f"species {s} {k}: {rel(pa[k], pb[k]):.2e}"
     ia, ib = a.get_info(), b.get_info()
     assert ia["step"] == ib["step"] and ia["alive"] == ib["alive"]
@@ -269,3 +269,31 @@ def test_set_tiles_and_autotune(pic):
     compare(b, a, 2, TOL64)
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("precision", [picgen.PREC_FP64, picgen.PREC_MIXED])
+def test_batch_with_per_particle_densities(pic, precision):
+    """Members carrying per-particle densities next to members with one density per species:
+    the batch runs the kernel with per-particle densities for all and matches the solo runs."""
+    wls = workloads(precision)
+    wls = [picgen.with_particle_densities(wl, seed=i) if i % 2 == 0 else wl
+           for i, wl in enumerate(wls)]
+    if precision == picgen.PREC_MIXED:
+        wls = [picgen.fp32_representable(wl) for wl in wls]
+    tol = TOL64 if precision == picgen.PREC_FP64 else TOLMIX
+    _say(f"batch with per-particle densities precision={precision}")
+    solo = [make(pic, wl, precision, i) for i, wl in enumerate(wls)]
+    mem = [make(pic, wl, precision, i) for i, wl in enumerate(wls)]
+    b = pic.Batch(0, precision)
+    b.set_graph(True)
+    for c in mem:
+        b.add(c)
+    for _ in range(2):
+        b.step(2)
+        for c in solo:
+            c.step(2)
+        for i, wl in enumerate(wls):
+            compare(mem[i], solo[i], len(wl.species), tol)
+    b.close()
+    for c in solo + mem:
+        c.close()

@@ -73,7 +73,9 @@ def setup_both(pic, wl, *, fields=None, tile=(0, 0), track_ids=True):
 
 
 def species_tuples(wl, parts):
-    return [(sp.q, sp.m, sp.w, p["xi_x"], p["xi_z"], p["ux"], p["uy"], p["uz"])
+    """(q, m, w, positions, momenta) per species; the densities come with the particle lists
+    (one per particle, in their order)."""
+    return [(sp.q, sp.m, p["w"], p["xi_x"], p["xi_z"], p["ux"], p["uy"], p["uz"])
             for sp, p in zip(wl.species, parts)]
 
 
@@ -202,7 +204,7 @@ def check_fields_and_moments(ctx, orc, wl, gparts, E, H):
     ref = OracleSim(wl.grid)
     ref.load_fields(E, H)
     for s, (sp, g) in enumerate(zip(wl.species, gparts)):
-        ref.load_species(s, sp.q, sp.m, sp.w, g["xi_x"], g["xi_z"], g["ux"], g["uy"], g["uz"])
+        ref.load_species(s, sp.q, sp.m, g["w"], g["xi_x"], g["xi_z"], g["ux"], g["uy"], g["uz"])
     scale = abs_deposit_scale(nx, nz, wl.grid.bc_x, wl.grid.dt, species_tuples(wl, gparts), H)
     check_moments_vs(ctx.read_moments(), ref.moments(), scale, what="step")
     # and against the oracle's own step (different by the FP32 push; cells can change)
@@ -232,6 +234,7 @@ def compare_step_unlabelled(ctx, orc, wl):
                 ok &= np.minimum(d, span - d) <= X_TOL
             for k in ("ux", "uy", "uz"):
                 ok &= np.abs(g[k][a] - o[k][b]) <= U_TOL * (1.0 + np.abs(o[k][b]))
+            ok &= g["w"][a] == o["w"][b]   # FP32-representable densities travel unchanged
             return ok
 
         jg, jo, eg, eo = align_sorted(g, o, nx, close)
@@ -402,5 +405,25 @@ def test_mixed_full_size_unlabelled(pic, name):
     ctx.step(1)
     orc.step(1)
     compare_step_unlabelled(ctx, orc, wl)
+    assert ctx.get_info()["overflow_flags"] == 0
+    ctx.close()
+
+
+@pytest.mark.parametrize("labels", [True, False])
+@pytest.mark.parametrize("wi", [0, 1, 3])
+def test_mixed_per_particle_densities(pic, wi, labels):
+    """Per-particle densities in the mixed form (stored as FP32; the inputs are FP32
+    representable): one cycle from identical state against the FP64 oracle."""
+    wl = picgen.fp32_representable(picgen.with_particle_densities(SMALL[wi], seed=40 + wi))
+    _say(f"mixed per-particle densities {wl.name} labels={labels}")
+    fields = picgen.random_fields(100 + wi, wl.grid)
+    ctx, orc = setup_both(pic, wl, fields=fields, tile=(8, 2), track_ids=labels)
+    prev = [ctx.read_particles(s, ids=True)["id"] for s in range(len(wl.species))] if labels else None
+    ctx.step(1)
+    orc.step(1)
+    if labels:
+        compare_step(ctx, orc, wl, prev)
+    else:
+        compare_step_unlabelled(ctx, orc, wl)
     assert ctx.get_info()["overflow_flags"] == 0
     ctx.close()

@@ -102,6 +102,7 @@ def check_particles(ctx, orc, wl, tol=TOL, ids=True):
                 ok &= d <= tol * span
             for k in ("ux", "uy", "uz"):
                 ok &= np.abs(g[k][a] - o[k][b]) <= tol * scale[k]
+            ok &= g["w"][a] == o["w"][b]   # densities travel with their particles unchanged
             if ids:
                 ok &= g["id"][a] == o["id"][b]
             return ok
@@ -399,3 +400,116 @@ def test_count_matched_foils_full_size_one_cycle(pic, name):
     check_particles(ctx, orc, wl, ids=False)
     assert ctx.get_info()["overflow_flags"] == 0
     ctx.close()
+
+
+@pytest.mark.parametrize("ids", [True, False])
+@pytest.mark.parametrize("tile", [(0, 0), (8, 2)])
+@pytest.mark.parametrize("wi", [0, 1, 3, 5])
+def test_per_particle_densities(pic, wi, tile, ids):
+    """Every particle carries its own density (Sec. 2: the current of particle alpha is
+    n_alpha q_alpha v_alpha): random densities per particle, deposit of the loaded state and
+    three cycles against the oracle, with and without particle labels.  The densities travel
+    with their particles through the sort."""
+    wl = picgen.with_particle_densities(SMALL[wi], seed=wi)
+    _say(f"per-particle densities {wl.name} tile={tile} ids={ids}")
+    fields = picgen.random_fields(300 + wi, wl.grid, amp_e=0.05, amp_h=0.2)
+    ctx, orc = setup_both(pic, wl, fields=fields, tile=tile, track_ids=ids)
+    check_moments(ctx, orc)
+    for _ in range(3):
+        ctx.step(1)
+        orc.step(1)
+        check_fields(ctx, orc)
+        check_moments(ctx, orc)
+        check_particles(ctx, orc, wl, ids=ids)
+    info = ctx.get_info()
+    assert info["overflow_flags"] == 0 and info["absorbed"] == orc.absorbed
+    ctx.close()
+
+
+def test_per_particle_densities_mixed_with_uniform_species(pic):
+    """One species with per-particle densities and one with a single density in the same
+    context (the kernels read the single density with stride 0), including reloading the
+    per-particle species with a single density again."""
+    base = SMALL[1]
+    wl = picgen.with_particle_densities(base, seed=9)
+    wl.species[1] = base.species[1].copy()
+    _say("per-particle and single densities together")
+    ctx, orc = setup_both(pic, wl, fields=picgen.random_fields(77, wl.grid, amp_e=0.05, amp_h=0.2))
+    for _ in range(2):
+        ctx.step(1)
+        orc.step(1)
+    check_fields(ctx, orc)
+    check_moments(ctx, orc)
+    check_particles(ctx, orc, wl)
+    g1 = ctx.read_particles(1)
+    assert np.all(g1["w"] == base.species[1].w)
+    # back to a single density for species 0: the kernels without per-particle densities run
+    p0 = ctx.read_particles(0)
+    ctx.load_particles(0, base.species[0].q, base.species[0].m, 0.5, p0["xi_x"], p0["xi_z"],
+                       p0["ux"], p0["uy"], p0["uz"])
+    orc.load_species(0, base.species[0].q, base.species[0].m, 0.5, p0["xi_x"], p0["xi_z"],
+                     p0["ux"], p0["uy"], p0["uz"])
+    check_moments(ctx, orc)
+    ctx.close()
+
+
+def test_allocator_hook_out_of_memory(pic):
+    """With an allocator hook that returns no memory, creating a context fails with
+    PIC_ERR_OOM; with one that stops giving memory after the grid, loading particles fails with
+    PIC_ERR_OOM and leaves the species empty.  With PyTorch's caching allocator behind the
+    hook, a run gives the result of a run on hipMalloc, and every block the library took is
+    back in torch's pool once the context is destroyed."""
+    import torch
+    wl = SMALL[3]
+    fields = picgen.random_fields(500, wl.grid)
+    _say("allocator hook")
+    refused = {"n": 0}
+    budget = {"left": 0}
+
+    def refuse(nbytes, device):
+        refused["n"] += 1
+        return 0
+
+    def limited(nbytes, device):
+        if budget["left"] <= 0:
+            return 0
+        budget["left"] -= 1
+        return torch.cuda.caching_allocator_alloc(int(nbytes), device=device)
+
+    def give_back(ptr, nbytes, device):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    try:
+        pic.set_allocator(refuse, give_back)
+        with pytest.raises(pic.PicError) as e:
+            pic.Context(wl.grid)
+        assert e.value.status == 2 and refused["n"] >= 1   # PIC_ERR_OOM
+        pic.set_allocator(limited, give_back)
+        budget["left"] = 10 ** 6
+        ctx = pic.Context(wl.grid)
+        budget["left"] = 0
+        sp = wl.species[0]
+        with pytest.raises(pic.PicError) as e:
+            ctx.load_particles(0, sp.q, sp.m, sp.w, sp.xi_x, sp.xi_z, sp.ux, sp.uy, sp.uz)
+        assert e.value.status == 2
+        assert ctx.get_info()["alive"][0] == 0
+        ctx.close()
+        assert torch.cuda.memory_allocated() == before
+        pic.use_torch_allocator()
+        a, _ = setup_both(pic, wl, fields=fields)
+        torch.cuda.synchronize()
+        assert torch.cuda.memory_allocated() - before >= a.get_info()["device_bytes"] > 0
+    finally:
+        pic.set_allocator(None, None)
+    b, _ = setup_both(pic, wl, fields=fields)
+    a.step(2)
+    b.step(2)
+    Ma, Mb = a.read_moments(), b.read_moments()
+    for p in range(Ma.shape[0]):
+        assert rel_err(Ma[p], Mb[p]) <= 1e-12
+    a.close()
+    b.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == before
