@@ -222,6 +222,17 @@ pic_status pic_set_mover(pic_ctx *ctx, int32_t options);
  * PIC_ERR_ARG (out NULL or len too small). */
 pic_status pic_energy(pic_ctx *ctx, double *out, int32_t len);
 
+/* pic_energy for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same energies, computed without
+ * any allocation.  Partial sums go to a fixed buffer in the library's device memory, one copy
+ * per GPU held until the process ends ((1024 + 1) x 9 doubles, 73,800 bytes, the largest
+ * species count included), and are added in a fixed order, so repeated calls on the same
+ * state give the same bits.  Calls that overlap on one GPU (other host threads, other
+ * contexts on the device) race on that buffer and must be serialised by the caller.  Waits for
+ * the context's stream.  Errors: as pic_energy (PIC_ERR_ARG for out NULL or len < 1 +
+ * n_species), PIC_ERR_DEVICE. */
+pic_status pic_energy_noalloc(pic_ctx *ctx, double *out, int32_t len);
+
 /* Device memory.  By default a context (and a batch) allocates with hipMalloc and releases
  * with hipFree.  pic_set_allocator installs a process-wide pair of functions used instead by
  * every context and batch created after the call (each keeps the pair it was created with):

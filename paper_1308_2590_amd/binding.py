@@ -25,7 +25,7 @@ EXPORTED = ["pic_init_grid", "pic_load_particles", "pic_load_fields", "pic_set_t
             "pic_set_step", "pic_step",
             "pic_read_moments", "pic_read_fields", "pic_read_particles", "pic_get_info",
             "pic_set_stream", "pic_sync", "pic_profile_enable", "pic_profile_read",
-            "pic_set_mover", "pic_energy", "pic_set_allocator",
+            "pic_set_mover", "pic_energy", "pic_energy_noalloc", "pic_set_allocator",
             "pic_last_error", "pic_destroy",
             "pic_batch_create", "pic_batch_add", "pic_batch_remove", "pic_batch_step",
             "pic_batch_set_graph", "pic_batch_sync", "pic_batch_size", "pic_batch_last_error",
@@ -105,6 +105,7 @@ def load_library(path: str = LIB_PATH):
         "pic_profile_read": ([P, C.POINTER(Profile)], C.c_int),
         "pic_set_mover": ([P, I32], C.c_int),
         "pic_energy": ([P, P, I32], C.c_int),
+        "pic_energy_noalloc": ([P, P, I32], C.c_int),
         "pic_set_allocator": ([ALLOC_FN, FREE_FN, P], C.c_int),
         "pic_last_error": ([P], C.c_char_p),
         "pic_destroy": ([P], None),
@@ -229,6 +230,12 @@ class Context:
         """[field energy, kinetic energy of species 0, 1, ...] of the current state."""
         out = np.zeros(1 + self.S)
         self._check(self.lib.pic_energy(self.h, _p(out), len(out)))
+        return [float(v) for v in out]
+
+    def energy_noalloc(self):
+        """energy() through the entry point that allocates no device memory."""
+        out = np.zeros(1 + self.S)
+        self._check(self.lib.pic_energy_noalloc(self.h, _p(out), len(out)))
         return [float(v) for v in out]
 
     def set_step(self, step):

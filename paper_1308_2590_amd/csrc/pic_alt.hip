@@ -18,6 +18,8 @@
 // differ from particle to particle, so these kernels deposit each particle's expanded moments
 // instead of per-cell sums; they trade speed for the choice.
 
+#include <mutex>
+
 #include "pic_internal.h"
 
 namespace pic {
@@ -277,7 +279,102 @@ __global__ __launch_bounds__(kBlock) void k_energy(const StepArgs a, const doubl
   }
 }
 
+// ---- energy without device allocation ----------------------------------------------------
+// The same sums as k_energy, reduced in a fixed order: every block writes its partial sums
+// (field, then each species slot) to its own row of a fixed buffer, and one block adds the rows
+// in block order.  Every value is written before it is read, so nothing needs clearing, and
+// the result does not depend on the timing of the blocks.
+
+__global__ __launch_bounds__(kBlock) void k_energy_partials(const StepArgs a, const double *E,
+                                                            const double *H, double *part) {
+  __shared__ double sh[kBlock / 64];
+  const GridArgs &g = a.g;
+  const double area = g.dx * g.dz;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  double *row = part + (size_t)blockIdx.x * kEnergyVals;
+  double f = 0.0;
+  for (int64_t e = tid; e < 3 * g.nnodes; e += stride) f += E[e] * E[e];
+  for (int64_t e = tid; e < 3 * g.ncells; e += stride) f += H[e] * H[e];
+  const double fs = block_sum(f, sh);
+  if (threadIdx.x == 0) row[0] = 0.5 * fs * area;
+  for (int s = 0; s < kMaxSpecies; ++s) {
+    if (s >= a.nsp || !a.sp[s].active) {
+      if (threadIdx.x == 0) row[1 + s] = 0.0;
+      continue;
+    }
+    const SpeciesArgs &sp = a.sp[s];
+    const int n = sp.cs[g.ncells];
+    double kin = 0.0;
+    for (int64_t j = tid; j < n; j += stride) {
+      const int p = sp.perm[j];
+      double u0, u1, u2, wp = 1.0;
+      if (a.mixed) {
+        u0 = (double)sp.msrc[2][p];
+        u1 = (double)sp.msrc[3][p];
+        u2 = (double)sp.msrc[4][p];
+        if (sp.w_stride) wp = (double)sp.msrc_w[p];
+      } else {
+        u0 = sp.src[2][p];
+        u1 = sp.src[3][p];
+        u2 = sp.src[4][p];
+        if (sp.w_stride) wp = sp.src_w[p];
+      }
+      kin += wp * (sqrt(1.0 + u0 * u0 + u1 * u1 + u2 * u2) - 1.0);
+    }
+    const double ks = block_sum(kin, sh);
+    const double wsp = sp.w_stride ? 1.0 : sp.w;
+    if (threadIdx.x == 0) row[1 + s] = ks * wsp * sp.m * area;
+  }
+}
+
+// Totals: thread v adds column v of the kEnergyBlocks rows in row order.
+__global__ void k_energy_total(const double *part, double *total) {
+  const int v = threadIdx.x;
+  if (v >= kEnergyVals) return;
+  double t = 0.0;
+  for (int b = 0; b < kEnergyBlocks; ++b) t += part[(size_t)b * kEnergyVals + v];
+  total[v] = t;
+}
+
+// The fixed buffer: kEnergyBlocks rows of partial sums, then the kEnergyVals totals.  One copy
+// per GPU, kept until the process ends; every call on a GPU uses that GPU's copy.
+static __device__ __align__(256) double scratch[kEnergyScratchDoubles];
+
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxScratchDevices] = {};
+
 }  // namespace
+
+hipError_t energy_scratch(int32_t device, double **ptr) {
+  *ptr = nullptr;
+  if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    // the address of this device's copy, looked up once with the device current (the array's
+    // name in host code is not a device address)
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<double *>(p);
+  }
+  *ptr = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
+hipError_t launch_energy_scratch(const StepArgs &a, const double *E, const double *H,
+                                 double *scratch_ptr, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy_partials, dim3(kEnergyBlocks), dim3(kBlock), 0, s, a, E, H,
+                     scratch_ptr);
+  hipLaunchKernelGGL(k_energy_total, dim3(1), dim3(64), 0, s, scratch_ptr,
+                     scratch_ptr + kEnergyBlocks * kEnergyVals);
+  return hipGetLastError();
+}
 
 hipError_t launch_particles_alt(const StepArgs &a, bool push, int mover, int32_t max_n,
                                 hipStream_t s) {

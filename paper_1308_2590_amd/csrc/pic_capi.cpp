@@ -949,6 +949,22 @@ pic_status pic_set_allocator(pic_alloc_fn alloc, pic_free_fn free_fn, void *user
   return PIC_OK;
 }
 
+pic_status pic_energy_noalloc(pic_ctx *c, double *out, int32_t len) {
+  if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
+  if (!out || len < 1 + c->S) return fail(c, PIC_ERR_ARG, "out must hold 1 + n_species values");
+  if (1 + c->S > pic::kEnergyVals)
+    return fail(c, PIC_ERR_ARG, "more species than the fixed energy buffer holds");
+  double *buf = nullptr;
+  HIP_TRY(c, pic::energy_scratch(c->d.device, &buf), "energy buffer address");
+  const pic::StepArgs a = step_args(c, false);
+  HIP_TRY(c, pic::launch_energy_scratch(a, c->E[c->ecur], c->H[c->hcur], buf, c->stream), "energy");
+  HIP_TRY(c, hipMemcpyAsync(out, buf + (size_t)pic::kEnergyBlocks * pic::kEnergyVals,
+                            (1 + (size_t)c->S) * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+          "read energy");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  return PIC_OK;
+}
+
 const char *pic_last_error(const pic_ctx *c) { return c ? c->err.c_str() : g_init_error.c_str(); }
 
 void pic_destroy(pic_ctx *c) {

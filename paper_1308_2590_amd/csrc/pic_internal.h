@@ -160,6 +160,17 @@ hipError_t launch_particles_alt(const StepArgs &a, bool push, int mover, int32_t
 // Field and kinetic energies into out[1 + nsp] (accumulated: zero it first).
 hipError_t launch_energy(const StepArgs &a, const double *E, const double *H, double *out,
                          hipStream_t s);
+// The same energies without device allocation: partial sums of kEnergyBlocks blocks in a
+// fixed per-device buffer, added in block order; the totals (field, then kMaxSpecies species
+// slots) end at scratch_ptr + kEnergyBlocks * kEnergyVals.
+constexpr int kEnergyBlocks = 1024;
+constexpr int kEnergyVals = 1 + kMaxSpecies;
+constexpr int kEnergyScratchDoubles = (kEnergyBlocks + 1) * kEnergyVals;  // 73,800 bytes
+constexpr int kMaxScratchDevices = 64;
+// Device address of that buffer on a HIP device (looked up once per device).
+hipError_t energy_scratch(int32_t device, double **ptr);
+hipError_t launch_energy_scratch(const StepArgs &a, const double *E, const double *H,
+                                 double *scratch_ptr, hipStream_t s);
 hipError_t launch_iota(int32_t *p, int64_t n, hipStream_t s);
 // One cycle of every run of a batch (field solve, particles, sort, counters).
 hipError_t launch_batch_cycle(const BatchArgs &b, const BatchLaunch &l, hipStream_t s);
