@@ -2,16 +2,19 @@
 """Benchmark of the implicit 2D3V PIC particle stage on one MI355X.
 
 A step is one full cycle of the hot path on the resident workload: field solve, fused
-gather-push-deposit, and the stable cell sort.  The workload defaults to the
-particle-dominated foil (1024 x 512 cells, absorbing x, periodic z, 40-cell slab at 100 n_c,
-64 particles per cell and species, about 2.6M particles, FP64).  Inputs are generated
-in host memory, loaded once, and are resident in HBM before the timed region starts.
+gather-push-deposit, and the stable cell sort.  The workload defaults to the largest
+single-GPU configuration, the field-dominated run (2048 x 2048 cells, absorbing x, periodic
+z, uniform 0.1 n_c, 4 particles per cell and species: 33.6M particles, FP64).  Inputs are
+generated in host memory, loaded once, and are resident in HBM before the timed region starts.
 
 Prints one JSON line with the throughput (alive particles x steps / s over whole cycles),
 the roofline position of the dominant kernel (the fused particle kernel) measured with HIP
-events on the stream the kernels run on, and the CPU oracle timed on a bounded sample.  The
-line also carries the FP64 / mixed-precision comparison: the same foil workload in both
-precisions, and the dense foil (200 n_c, 128 particles per cell and species) in both.
+events on the stream the kernels run on, and the CPU oracle timed on a bounded sample (one
+thread, and independent copies on all cores the job may use).  The line also carries the
+particle-dominated foil (1024 x 512 cells, 40-cell slab at 100 n_c, 64 particles per cell and
+species) with its own roofline, and the FP64 / mixed-precision comparison on the foil, the
+dense foil (200 n_c, 128 particles per cell and species) and the count-matched dense foil
+(160-cell slab, 21.0M particles).
 """
 from __future__ import annotations
 
@@ -77,8 +80,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="foil",
-                    help="foil | foil_cm | lowdensity | uniform64a | uniform64b")
+    ap.add_argument("--workload", default="lowdensity",
+                    help="lowdensity | foil | foil_cm | foil_dense | foil_dense_cm | uniform64a | uniform64b")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget for the CPU oracle baseline (0 disables it)")
     ap.add_argument("--tile", default="0",
@@ -90,9 +93,12 @@ def parse():
                     help="timed cycles of each FP64 / mixed comparison run (0 skips them)")
     ap.add_argument("--drift-steps", type=int, default=500,
                     help="cycles of the FP64 / mixed drift comparison on the dense foil (0 skips it)")
-    ap.add_argument("--field-steps", type=int, default=20,
-                    help="timed cycles of the field-dominated run (2048 x 2048, 33.6M particles; "
-                         "0 skips it)")
+    ap.add_argument("--foil-steps", type=int, default=50,
+                    help="timed cycles of the particle-dominated foil section (0 skips it)")
+    ap.add_argument("--cpu-cores", type=int, default=16,
+                    help="most host cores the all-cores oracle baseline may use")
+    ap.add_argument("--cpu-worker", default="",
+                    help=argparse.SUPPRESS)
     ap.add_argument("--mover-steps", type=int, default=1000,
                     help="cycles of the warm-plasma energy comparison of the mover options "
                          "(0 skips the mover-option section)")
@@ -109,10 +115,21 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(wl, budget_s):
-    """The oracle as it is (single-threaded C), on the same workload, for whole cycles until
-    the budget is used (at least one cycle)."""
+def cpu_sample(name):
+    """The bounded sample of a workload that the oracle runs: the field-dominated run as a
+    2048 x 64 strip (its full row length, cells, particles per cell, temperatures and laser,
+    1,048,576 particles), every other workload as it is."""
+    if name == "lowdensity":
+        return picgen.low_density(nz=64), "a 2048 x 64 strip of the 2048 x 2048 run (1,048,576 particles)"
+    wl = picgen.named(name)
+    return wl, f"the whole workload ({wl.n_particles} particles)"
+
+
+def cpu_run(name, budget_s):
+    """The oracle as it is (single-threaded C) on the sample of a workload: whole cycles until
+    the budget is used (at least one).  Returns (particle-steps, seconds, cycles)."""
     from oracle import OracleSim
+    wl, _ = cpu_sample(name)
     o = OracleSim(wl.grid)
     for s, sp in enumerate(wl.species):
         o.load_species(s, sp.q, sp.m, sp.w, sp.xi_x, sp.xi_z, sp.ux, sp.uy, sp.uz)
@@ -125,11 +142,53 @@ def cpu_baseline(wl, budget_s):
         steps += 1
         ps += n
         el = time.perf_counter() - t0
-        if el >= budget_s or steps >= 50:
+        if el >= budget_s or steps >= 200:
             break
-    return {"value": ps / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} full cycles of the same workload ({wl.name}) on one host core, "
-                      f"{el:.1f} s"}
+    return ps, el, steps
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(name, budget_s, max_cores):
+    """The oracle timed on the host cores of this job: one thread in this process, then
+    independent copies of the same sample in child processes, one per core (at most
+    max_cores, and no more than the cores this process may run on), at the same time.  The
+    value is the all-cores aggregate; the one-thread figure is beside it."""
+    import subprocess
+    _, what = cpu_sample(name)
+    ps, el, steps = cpu_run(name, budget_s)
+    one = ps / el
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    ncores = max(1, min(max_cores, avail))
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-worker", name,
+           "--cpu-seconds", str(budget_s)]
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    t0 = time.perf_counter()
+    procs = [subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, env=env, text=True)
+             for _ in range(ncores)]
+    rates = []
+    for p in procs:
+        out, _ = p.communicate()
+        if p.returncode == 0 and out.strip():
+            r = json.loads(out.strip().splitlines()[-1])
+            rates.append(r["particle_steps"] / r["seconds"])
+    wall = time.perf_counter() - t0
+    return {"value": sum(rates) if rates else one, "unit": "particle-steps/s",
+            "cores": len(rates) if rates else 1, "kind": "oracle",
+            "sample": f"{what} of the {name} workload: the plain FP64 oracle, one thread per "
+                      f"process, whole cycles for about {budget_s:.0f} s; {len(rates)} copies ran "
+                      f"at once ({wall:.1f} s wall) for the all-cores value",
+            "single_thread_value": one, "single_thread_cycles": steps,
+            "single_thread_seconds": el, "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "cores_available": avail}
 
 
 PROFILE_EVERY = 4
@@ -166,6 +225,10 @@ def run_gpu(binding, torch, wl, precision, steps, warmup, tile, autotune=False):
     prof = ctx.profile_read()
     ctx.profile_enable(False)
     info1 = ctx.get_info()
+    # nodes the deposit reached (any moment plane nonzero): the node part of the kernel's work
+    M = ctx.read_moments()
+    touched = int(np.count_nonzero(np.any(M != 0.0, axis=0)))
+    del M
     ctx.close()
     if info1["overflow_flags"]:
         print(f"overflow flags raised: {info1['overflow_flags']}", file=sys.stderr)
@@ -175,6 +238,7 @@ def run_gpu(binding, torch, wl, precision, steps, warmup, tile, autotune=False):
     n_mean = 0.5 * (n_alive0 + n_alive1)
     part_ms = prof["particle_ms"] / max(prof["particle_launches"], 1)
     alg_bytes = BYTES_PER_PARTICLE[precision] * n_mean + bytes_per_node(S) * wl.grid.n_nodes
+    alg_bytes_touched = BYTES_PER_PARTICLE[precision] * n_mean + bytes_per_node(S) * touched
     achieved = alg_bytes / (part_ms * 1e-3) / 1e9
     return {
         "autotune": None if tuned is None else {
@@ -187,7 +251,10 @@ def run_gpu(binding, torch, wl, precision, steps, warmup, tile, autotune=False):
         "tile": list(info1["tile"]),
         "part_ms": part_ms,
         "alg_bytes": alg_bytes,
+        "alg_bytes_touched": alg_bytes_touched,
+        "nodes_touched": touched,
         "achieved": achieved,
+        "achieved_touched": alg_bytes_touched / (part_ms * 1e-3) / 1e9,
         "breakdown": {
             "field_solve": prof["field_ms"] / max(prof["field_launches"], 1),
             "particles": part_ms,
@@ -204,6 +271,7 @@ def comparison(binding, torch, wl, steps, warmup, tile, autotune):
         r[prec] = {"particle_steps_per_s": m["value"], "ms_per_step": m["ms_per_step"],
                    "particle_kernel_ms": m["part_ms"], "particle_kernel_GBps": m["achieved"],
                    "particle_kernel_frac_hbm": m["achieved"] / HBM_PEAK_GBS,
+                   "particle_kernel_frac_hbm_touched_nodes": m["achieved_touched"] / HBM_PEAK_GBS,
                    "tile": m["tile"]}
     r["speedup_mixed_over_fp64"] = r["mixed"]["particle_steps_per_s"] / r["fp64"]["particle_steps_per_s"]
     r["particle_kernel_speedup"] = r["fp64"]["particle_kernel_ms"] / r["mixed"]["particle_kernel_ms"]
@@ -257,15 +325,37 @@ def drift(binding, steps, name="foil_dense"):
             "mixed_vs_fp64_rounded_inputs": errs(runs["mixed"], runs["fp64_rounded_inputs"])}
 
 
-def field_dominated(binding, torch, steps, warmup):
-    """The field-dominated run (2048 x 2048 cells, uniform 0.1 n_c, 4 particles per cell and
-    species: 33.6M particles, laser a0 = 1) in FP64 with the library's tile choice: cycle time
-    and its split between the field solve, the particle kernel and the sort."""
-    wl = picgen.named("lowdensity")
-    m = run_gpu(binding, torch, wl, "fp64", steps, warmup, (0, 0))
-    return {"workload": wl.name, "particles": wl.n_particles, "cells": wl.grid.nx * wl.grid.nz,
-            "steps": steps, "ms_per_step": m["ms_per_step"], "particle_steps_per_s": m["value"],
-            "tile": m["tile"], "breakdown_ms_per_step": m["breakdown"]}
+def roofline(m, workload, precision):
+    """The roofline object of the particle kernel from a run_gpu measurement: algorithmic bytes
+    with every grid node (the moments are defined on the whole grid), and with the nodes the
+    deposit reached (the kernel touches only the tiles holding particles)."""
+    return {
+        "bound": "hbm",
+        "kernel": "k_particles (fused gather-push-deposit)",
+        "achieved": m["achieved"],
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": m["achieved"] / HBM_PEAK_GBS,
+        "traffic": measured_traffic(workload, precision, m["tile"]),
+        "alg_bytes_per_launch": m["alg_bytes"],
+        "avg_launch_ms": m["part_ms"],
+        "alg_bytes_per_launch_touched_nodes": m["alg_bytes_touched"],
+        "nodes_touched": m["nodes_touched"],
+        "achieved_touched_nodes": m["achieved_touched"],
+        "frac_touched_nodes": m["achieved_touched"] / HBM_PEAK_GBS,
+    }
+
+
+def particle_dominated(binding, torch, steps, warmup, auto):
+    """The particle-dominated foil (1024 x 512 cells, 40-cell slab at 100 n_c, 64 particles per
+    cell and species: 2.62M particles) in FP64: throughput, cycle breakdown and the particle
+    kernel's roofline."""
+    wl = picgen.named("foil")
+    m = run_gpu(binding, torch, wl, "fp64", steps, warmup, (0, 0), autotune=auto)
+    return {"workload": wl.name, "particles": m["particles"], "steps": steps,
+            "particle_steps_per_s": m["value"], "ms_per_step": m["ms_per_step"], "tile": m["tile"],
+            "breakdown_ms_per_step": m["breakdown"], "roofline": roofline(m, "foil", "fp64"),
+            "autotune": m["autotune"]}
 
 
 def warm_plasma(temperature_kev, nx=128, nz=128, ppc=16):
@@ -393,6 +483,11 @@ def serving(args):
 
 def main():
     args = parse()
+    if args.cpu_worker:
+        # child of cpu_baseline: one copy of the oracle on its sample, no GPU
+        ps, el, steps = cpu_run(args.cpu_worker, args.cpu_seconds)
+        print(json.dumps({"particle_steps": ps, "seconds": el, "cycles": steps}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "strip decomposition is not part of this build", file=sys.stderr)
@@ -437,33 +532,23 @@ def main():
             "tile": m["tile"],
             "note": wl.note,
         },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_particles (fused gather-push-deposit)",
-            "achieved": m["achieved"],
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": m["achieved"] / HBM_PEAK_GBS,
-            "traffic": measured_traffic(args.workload, args.precision, m["tile"]),
-            "alg_bytes_per_launch": m["alg_bytes"],
-            "avg_launch_ms": m["part_ms"],
-        },
+        "roofline": roofline(m, args.workload, args.precision),
         "breakdown_ms_per_step": m["breakdown"],
         "autotune": m["autotune"],
     }
+    if args.foil_steps > 0 and args.workload != "foil":
+        out["particle_dominated"] = particle_dominated(binding, torch, args.foil_steps,
+                                                       args.warmup, bool(args.autotune))
+        print("[bench] particle-dominated foil done", file=sys.stderr, flush=True)
     if args.compare_steps > 0:
         out["fp64_vs_mixed"] = [
-            comparison(binding, torch, wl, args.compare_steps, args.warmup, tile, auto),
-            comparison(binding, torch, picgen.named("foil_dense"), args.compare_steps,
-                       args.warmup, tile, auto),
-        ]
+            comparison(binding, torch, picgen.named(name), args.compare_steps, args.warmup,
+                       (0, 0), bool(args.autotune))
+            for name in ("foil", "foil_dense", "foil_dense_cm")]
         print("[bench] comparison done", file=sys.stderr, flush=True)
     if args.drift_steps > 0:
         out["precision_drift"] = drift(binding, args.drift_steps)
         print("[bench] drift done", file=sys.stderr, flush=True)
-    if args.field_steps > 0:
-        out["field_dominated"] = field_dominated(binding, torch, args.field_steps, args.warmup)
-        print("[bench] field-dominated run done", file=sys.stderr, flush=True)
     if args.mover_steps > 0:
         out["mover_options"] = mover_options(binding, torch, args.mover_steps)
         print("[bench] mover options done", file=sys.stderr, flush=True)
@@ -475,7 +560,8 @@ def main():
         out["serving"] = serving(args)
         print("[bench] serving done", file=sys.stderr, flush=True)
     if args.cpu_seconds > 0:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds, args.cpu_cores)
+        print("[bench] cpu baseline done", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 
