@@ -56,6 +56,22 @@ __device__ __forceinline__ int wrap_any(int i, int n) {
   return i < 0 ? i + n : i;
 }
 
+// Wrap onto [0, n): one conditional add or subtract when i is known to lie in [-n, 2n) (near:
+// a tile and its ring fit in the grid), the general remainder otherwise (grids smaller than a
+// tile).  near is the same for the whole block.
+__device__ __forceinline__ int wrap_t(int i, int n, bool near) {
+  return near ? wrap1(i, n) : wrap_any(i, n);
+}
+
+// Quotient e / d of small non-negative integers (e < 2^16, 0 < d < 2^12) from one multiply:
+// (e + 1/2) / d lies at least 1 / (2 d) away from every integer, far more than the rounding of
+// the float product, so truncating it gives the exact quotient.
+struct SmallDiv {
+  float r;
+  __device__ __forceinline__ explicit SmallDiv(int d) : r(1.0f / (float)d) {}
+  __device__ __forceinline__ int q(int e) const { return (int)(((float)e + 0.5f) * r); }
+};
+
 // The tile handled by this block, taken from the ordered list of tiles that hold particles:
 // blocks are dealt round-robin to the 8 XCDs, so each XCD gets a contiguous band of the list
 // (neighbouring tiles share halo nodes and field cache lines).  Surplus blocks return.
@@ -688,6 +704,8 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
   const int n_acc = Lo.n_node * plane + 12 * Lo.NPL;  // node planes, then cell-corner planes
 
   for (int e = threadIdx.x; e < n_acc; e += blockDim.x) acc.node[e] = 0.0;
+  // a tile and its two-cell ring fit in the grid along an axis: wraps need one compare there
+  const bool nearx = g.nx >= t.tx + 3, nearz = g.nz >= t.tz + 3;
   // Stage the fields of the tile and the slot range of every tile row of every species in one
   // pass: a thread issues all its loads (at clamped, valid addresses) before it stores any, so
   // the block waits for one memory round trip instead of one per array.
@@ -697,7 +715,7 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
   for (int e = threadIdx.x; e < n_stage; e += blockDim.x) {
     // H^{n+1/2} on the tile's cells
     const int eh = min(e, Lo.HPL - 1);
-    const int hk = eh / t.tx, hi = eh - hk * t.tx;
+    const int hk = SmallDiv(t.tx).q(eh), hi = eh - hk * t.tx;
     const bool h_in = e < Lo.HPL && i0 + hi < g.nx && k0 + hk < g.nz;
     const int64_t ch = (int64_t)min(k0 + hk, g.nz - 1) * g.nx + min(i0 + hi, g.nx - 1);
     double ho[3];
@@ -721,11 +739,11 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
     if (PUSH) {
       // E-bar on the tile's nodes
       const int ee = min(e, Lo.EPL - 1);
-      const int ek = ee / Lo.EW, ei = ee - ek * Lo.EW;
+      const int ek = SmallDiv(Lo.EW).q(ee), ei = ee - ek * Lo.EW;
       int gi = i0 + ei;
-      const int gk = wrap_any(k0 + ek, g.nz);
+      const int gk = wrap_t(k0 + ek, g.nz, nearz);
       e_in = e < Lo.EPL;
-      if (g.bc_x == PIC_BC_PERIODIC) gi = wrap_any(gi, g.nx); else e_in = e_in && gi <= g.nx;
+      if (g.bc_x == PIC_BC_PERIODIC) gi = wrap_t(gi, g.nx, nearx); else e_in = e_in && gi <= g.nx;
       const int64_t n = (int64_t)gk * g.nxn + min(gi, g.nxn - 1);
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
@@ -734,11 +752,11 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
       }
       // H^{n+3/2} on the tile's cells and their ring
       const int en_ = min(e, Lo.NPL - 1);
-      const int nk = en_ / Lo.NW, ni = en_ - nk * Lo.NW;
+      const int nk = SmallDiv(Lo.NW).q(en_), ni = en_ - nk * Lo.NW;
       int gi2 = i0 - 1 + ni;
-      const int gk2 = wrap_any(k0 - 1 + nk, g.nz);
+      const int gk2 = wrap_t(k0 - 1 + nk, g.nz, nearz);
       n_in = e < Lo.NPL;
-      if (g.bc_x == PIC_BC_PERIODIC) gi2 = wrap_any(gi2, g.nx); else n_in = n_in && gi2 >= 0 && gi2 < g.nx;
+      if (g.bc_x == PIC_BC_PERIODIC) gi2 = wrap_t(gi2, g.nx, nearx); else n_in = n_in && gi2 >= 0 && gi2 < g.nx;
       const int64_t c2 = (int64_t)gk2 * g.nx + min(max(gi2, 0), g.nx - 1);
 #pragma unroll
       for (int q = 0; q < 3; ++q) hn[q] = a.Hnew[q * nc + c2];
@@ -802,12 +820,13 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
     // A tile with fewer rows than wavefronts splits each row's particles into wpr contiguous
     // parts, one per wavefront, so short tiles keep every wavefront busy.
     const int nrows = k1 - k0;
-    const int wpr = nrows < nwaves ? nwaves / nrows : 1;
+    const int wpr = nrows < nwaves ? nwaves / nrows : 1;  // 1, 2 or 4 (four wavefronts)
+    const int wsh = wpr == 4 ? 2 : (wpr == 2 ? 1 : 0);
     const int part = wave % wpr;
     for (int r = k0 + wave / wpr; r < k1; r += nwaves / wpr) {
       const int rb = rowsL[2 * (s * nrows_t + (r - k0))], re = rowsL[2 * (s * nrows_t + (r - k0)) + 1];
-      const int jb = rb + (int)((int64_t)(re - rb) * part / wpr);
-      const int je = rb + (int)((int64_t)(re - rb) * (part + 1) / wpr);
+      const int jb = rb + (int)(((uint32_t)(re - rb) * (uint32_t)part) >> wsh);
+      const int je = rb + (int)(((uint32_t)(re - rb) * (uint32_t)(part + 1)) >> wsh);
       const int L = je - jb;
       if (L == 0) continue;
       const int q = L >> 6, rr = L & 63;
@@ -1101,19 +1120,23 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
       for (int e = threadIdx.x; e < AW * AH; e += blockDim.x) arrL[e] = 0;
       __syncthreads();
       const int cw = i1 - i0, chh = k1 - k0;
-      for (int e = threadIdx.x; e < chh * cw * kMoveCodes; e += blockDim.x) {
-        const int d = e / (chh * cw);
-        const int rem = e - d * (chh * cw);
-        const int lkk = rem / cw, li = rem - lkk * cw;
-        const int v = cntL[(lkk * t.tx + li) * 10 + d];
-        sp.cnt[(int64_t)d * nc + (int64_t)(k0 + lkk) * g.nx + (i0 + li)] = v;
-        if (v) atomicAdd(&arrL[(lkk + 1 + d / 3 - 1) * AW + (li + 1 + d % 3 - 1)], v);
+      const SmallDiv div_cw(cw);
+      for (int e = threadIdx.x; e < chh * cw; e += blockDim.x) {
+        const int lkk = div_cw.q(e), li = e - lkk * cw;
+        const int64_t cg = (int64_t)(k0 + lkk) * g.nx + (i0 + li);
+        const int *cl = cntL + (lkk * t.tx + li) * 10;
+#pragma unroll
+        for (int d = 0; d < kMoveCodes; ++d) {
+          const int v = cl[d];
+          sp.cnt[(int64_t)d * nc + cg] = v;
+          if (v) atomicAdd(&arrL[(lkk + d / 3) * AW + (li + d % 3)], v);
+        }
       }
       __syncthreads();
       for (int e = threadIdx.x; e < AW * AH; e += blockDim.x) {
         const int v = arrL[e];
         if (v == 0) continue;
-        const int az = e / AW, ax = e - az * AW;
+        const int az = SmallDiv(AW).q(e), ax = e - az * AW;
         int gi = i0 - 1 + ax;
         const int gk = wrap1(k0 - 1 + az, g.nz);
         if (g.bc_x == PIC_BC_PERIODIC) gi = wrap1(gi, g.nx);
@@ -1131,32 +1154,28 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
     int gx = i0 + (sx < 3 ? sx - 1 : t.tx + sx - 4);
     int gz = k0 + (sz < 3 ? sz - 1 : t.tz + sz - 4);
     bool in = true;
-    if (g.bc_x == PIC_BC_PERIODIC) gx = wrap_any(gx, g.nx); else in = gx >= 0 && gx <= g.nx;
-    gz = wrap_any(gz, g.nz);
+    if (g.bc_x == PIC_BC_PERIODIC) gx = wrap_t(gx, g.nx, nearx); else in = gx >= 0 && gx <= g.nx;
+    gz = wrap_t(gz, g.nz, nearz);
     if (in) a.mtile[(gz / t.tz) * t.ntx + min(gx, g.nx - 1) / t.tx] = 1;
   }
-  // Fold the tile's accumulators into the global FP64 moment planes: delta-j and density as
-  // they are; S-hat at a node from the S-hat scalars of the (up to) four cells around it, each
-  // expanded with its cell's B (H^{n+3/2} after a push, H^{n+1/2} for a deposit of the current
-  // state): S-hat = a0 I + a1 [B]x + a2 B B^T.
-  for (int e = threadIdx.x; e < Lo.n_node * plane; e += blockDim.x) {
-    const double v = acc.node[e];
-    if (v == 0.0) continue;
-    const int pp = e / plane, idx = e - pp * plane;
-    const int lzz = idx / LW, lx = idx - lzz * LW;
-    int gx = i0 - 1 + lx, gz = k0 - 1 + lzz;
-    if (g.bc_x == PIC_BC_PERIODIC) {
-      gx = wrap_any(gx, g.nx);
-    } else if (gx < 0 || gx > g.nx) {
-      continue;
-    }
-    gz = wrap_any(gz, g.nz);
-    const int gp = pp < 3 ? 9 + pp : 12 + (pp - 3);
-    unsafeAtomicAdd(&a.M[(int64_t)gp * nn + (int64_t)gz * g.nxn + gx], v);
-  }
+  // Fold the tile's accumulators into the global FP64 moment planes, one node per thread:
+  // delta-j and the densities as they are; S-hat from the S-hat scalars of the (up to) four
+  // cells around the node, each expanded with its cell's B (H^{n+3/2} after a push, H^{n+1/2}
+  // for a deposit of the current state): S-hat = a0 I + a1 [B]x + a2 B B^T.
   const int NH = t.tz + 2;
-  for (int e = threadIdx.x; e < plane; e += blockDim.x) {
-    const int lzz = e / LW, lx = e - lzz * LW;
+  const SmallDiv div_lw(LW);
+  for (int idx = threadIdx.x; idx < plane; idx += blockDim.x) {
+    const int lzz = div_lw.q(idx), lx = idx - lzz * LW;
+    int gx = i0 - 1 + lx;
+    bool in = true;
+    if (g.bc_x == PIC_BC_PERIODIC) gx = wrap_t(gx, g.nx, nearx); else in = gx >= 0 && gx <= g.nx;
+    const int gz = wrap_t(k0 - 1 + lzz, g.nz, nearz);
+    const int64_t node = (int64_t)gz * g.nxn + gx;
+    for (int pp = 0; pp < Lo.n_node; ++pp) {
+      const double v = acc.node[pp * plane + idx];
+      const int gp = pp < 3 ? 9 + pp : 12 + (pp - 3);
+      if (in && v != 0.0) unsafeAtomicAdd(&a.M[(int64_t)gp * nn + node], v);
+    }
     double S[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     bool any = false;
 #pragma unroll
@@ -1190,15 +1209,7 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
       S[8] += fma(A2, B2 * B2, A0);
       any = true;
     }
-    if (!any) continue;
-    int gx = i0 - 1 + lx, gz = k0 - 1 + lzz;
-    if (g.bc_x == PIC_BC_PERIODIC) {
-      gx = wrap_any(gx, g.nx);
-    } else if (gx < 0 || gx > g.nx) {
-      continue;
-    }
-    gz = wrap_any(gz, g.nz);
-    const int64_t node = (int64_t)gz * g.nxn + gx;
+    if (!any || !in) continue;
 #pragma unroll
     for (int r = 0; r < 9; ++r)
       if (S[r] != 0.0) unsafeAtomicAdd(&a.M[(int64_t)r * nn + node], S[r]);
@@ -1355,17 +1366,20 @@ __device__ __forceinline__ void rank_body(const StepArgs &a, int tile, int speci
     // counts of the tile and a one-cell ring (sources of the destinations reached from the
     // tile), and next-order starts of the same region, staged in LDS
     const int RW = t.tx + 4, RH = t.tz + 4;  // ring of two cells: destinations +-1, their sources +-1
+    // a tile and its ring fit in the grid along an axis: wraps need one compare there
+    const bool nearx = g.nx >= t.tx + 4, nearz = g.nz >= t.tz + 4;
+    const SmallDiv div_rw(RW), div_tx(t.tx), div_tz(t.tz);
     for (int e = threadIdx.x; e < RW * RH; e += blockDim.x) {
-      const int rz = e / RW, rx = e - rz * RW;
+      const int rz = div_rw.q(e), rx = e - rz * RW;
       int gi = i0 - 2 + rx;
-      const int gk = wrap_any(k0 - 2 + rz, g.nz);
+      const int gk = wrap_t(k0 - 2 + rz, g.nz, nearz);
       bool in = true;
-      if (g.bc_x == PIC_BC_PERIODIC) gi = wrap_any(gi, g.nx); else in = gi >= 0 && gi < g.nx;
+      if (g.bc_x == PIC_BC_PERIODIC) gi = wrap_t(gi, g.nx, nearx); else in = gi >= 0 && gi < g.nx;
       // The counts are valid only in tiles that held particles (the tile flag); they are
       // loaded together with the flag (from a cell inside the grid) and kept or dropped after.
       const int gic = min(max(gi, 0), g.nx - 1);
       const int64_t c = (int64_t)gk * g.nx + gic;
-      const bool act = in && a.tile_active[cell_tile(t, gic, gk)] != 0;
+      const bool act = in && a.tile_active[div_tz.q(gk) * t.ntx + div_tx.q(gic)] != 0;
       int v[kMoveCodes];
 #pragma unroll
       for (int d = 0; d < kMoveCodes; ++d) v[d] = sp.cnt[(int64_t)d * g.ncells + c];
@@ -1378,9 +1392,12 @@ __device__ __forceinline__ void rank_body(const StepArgs &a, int tile, int speci
     __syncthreads();
     // (a tile without particles of this species has no counts: its table stays zero and its
     // rows are empty)
+    // one (code, cell) pair per thread, consecutive threads on consecutive cells of one code
+    // (so their LDS reads of the staged counts fall in different banks)
+    const SmallDiv div_cells(ch * cw), div_cw(cw);
     for (int e = threadIdx.x; e < ch * cw * kMoveCodes; e += blockDim.x) {
-      const int cell = e / kMoveCodes, d = e - cell * kMoveCodes;
-      const int lk = cell / cw, li = cell - lk * cw;
+      const int d = div_cells.q(e), cell = e - d * (ch * cw);
+      const int lk = div_cw.q(cell), li = cell - lk * cw;
       // First slot, in the next order, of the particles moving from this cell with code d:
       // the start of the destination cell plus the particles arriving there from source
       // cells earlier in the current (cell-sorted) order.  Destination and sources lie in
@@ -1644,9 +1661,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_counts(const StepArgs a) {
   for (int q = 0; q < kScan1Items; ++q) sum += in[q];
   if (sum) {
     int k = (int)(c0 / g.nx), i = (int)(c0 - (int64_t)k * g.nx);
+    const SmallDiv div_tx(a.t.tx), div_tz(a.t.tz);
 #pragma unroll
     for (int q = 0; q < kScan1Items; ++q) {
-      if (in[q] && k < g.nz) a.tile_active_next[cell_tile(a.t, i, k)] = 1;
+      if (in[q] && k < g.nz) a.tile_active_next[div_tz.q(k) * a.t.ntx + div_tx.q(i)] = 1;
       if (++i == g.nx) {
         i = 0;
         ++k;
