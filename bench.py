@@ -472,8 +472,17 @@ def serving(args):
     reqs = picgen.serving_stream(args.serve_runs, rate_per_s=args.serve_rate)
     srv = serve.Server(picgen.request_workload, precision=picgen.PREC_MIXED, max_slots=256,
                        budget_bytes=64 << 30, graph=True)
-    st = srv.run(reqs, realtime=True)
-    srv.close()
+    done = [0]
+
+    def progress(req, ctx):
+        done[0] += 1
+        if done[0] % 32 == 0:
+            print(f"[bench] serving: {done[0]} of {len(reqs)} runs done", file=sys.stderr, flush=True)
+
+    try:
+        st = srv.run(reqs, realtime=True, on_finish=progress)
+    finally:
+        srv.close()
     out = st.summary()
     out.update({"arrival_rate_per_s": args.serve_rate, "precision": "mixed", "graph": True,
                 "offered_particle_steps": float(sum(
@@ -489,8 +498,8 @@ def main():
         print(json.dumps({"particle_steps": ps, "seconds": el, "cycles": steps}), flush=True)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "strip decomposition is not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library has "
+              "no multi-GPU path (the strip decomposition across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1308_2590_amd import binding

@@ -23,7 +23,7 @@ struct pic_batch {
   pic::FieldArgs *d_field = nullptr; // [2 cap]
   int32_t *d_par = nullptr;          // [cap]
   int64_t *d_ctr = nullptr;          // [cap]
-  int32_t *d_pre = nullptr;          // [8][cap + 1]
+  int32_t *d_pre = nullptr;          // [6][cap + 1]
   pic::BatchArgs args{};
   pic::BatchLaunch launch{};
   int cus = 0;
@@ -87,7 +87,7 @@ pic_status grow(pic_batch *b, size_t n) {
   BHIP(b, b->mem.get((void **)&b->d_field, 2 * cap * sizeof(pic::FieldArgs)), "batch tables");
   BHIP(b, b->mem.get((void **)&b->d_par, cap * sizeof(int32_t)), "batch tables");
   BHIP(b, b->mem.get((void **)&b->d_ctr, cap * sizeof(int64_t)), "batch tables");
-  BHIP(b, b->mem.get((void **)&b->d_pre, 8 * (cap + 1) * sizeof(int32_t)), "batch tables");
+  BHIP(b, b->mem.get((void **)&b->d_pre, 6 * (cap + 1) * sizeof(int32_t)), "batch tables");
   b->cap = cap;
   return PIC_OK;
 }
@@ -102,7 +102,7 @@ pic_status rebuild(pic_batch *b) {
   std::vector<pic::FieldArgs> fields(2 * n);
   std::vector<int32_t> par(n);
   std::vector<int64_t> ctr(n);
-  std::vector<int32_t> pre(8 * (n + 1), 0);
+  std::vector<int32_t> pre(6 * (n + 1), 0);
   size_t lds_p = 0, lds_r = 0;
   bool ids = false, pw = false;
   for (size_t r = 0; r < n; ++r) {
@@ -115,30 +115,33 @@ pic_status rebuild(pic_batch *b) {
     for (int p = 0; p < 2; ++p) {
       steps[2 * r + p] = pic::cycle_step_args(c, p);
       fields[2 * r + p] = pic::cycle_field_args(c, p);
+      // the batched cycle clears the next order's tile flags in the H update
+      fields[2 * r + p].tact_next = c->tact[1 - p];
     }
     par[r] = c->cur;
     ctr[r] = c->step;
     const pic::GridArgs &g = c->g;
-    const int32_t items[6] = {
+    const int32_t items[4] = {
         (int32_t)((g.nnodes + pic::kSolveNodes * pic::kBlock - 1) / (pic::kSolveNodes * pic::kBlock)),
         (int32_t)((g.ncells + pic::kHCells * pic::kBlock - 1) / (pic::kHCells * pic::kBlock)),
-        c->n_scan_blocks * c->S,
-        c->S,
-        (c->tiles.ntiles + pic::kBlock - 1) / pic::kBlock,
+        c->n_scan1_blocks * c->S,
         1};
-    for (int k = 0; k < 6; ++k) pre[k * (n + 1) + r + 1] = pre[k * (n + 1) + r] + items[k];
+    for (int k = 0; k < 4; ++k) pre[k * (n + 1) + r + 1] = pre[k * (n + 1) + r] + items[k];
     lds_p = std::max(lds_p, pic::particle_lds_bytes(c->g, c->tiles, b->precision == PIC_PREC_MIXED, pw));
     lds_r = std::max(lds_r, pic::rank_lds_bytes(c->tiles));
   }
   if (n > 0) {
-    BHIP(b, hipMemcpy(b->d_step, steps.data(), steps.size() * sizeof(pic::StepArgs), hipMemcpyHostToDevice),
-         "upload batch tables");
-    BHIP(b, hipMemcpy(b->d_field, fields.data(), fields.size() * sizeof(pic::FieldArgs), hipMemcpyHostToDevice),
-         "upload batch tables");
-    BHIP(b, hipMemcpy(b->d_par, par.data(), n * sizeof(int32_t), hipMemcpyHostToDevice), "upload batch tables");
-    BHIP(b, hipMemcpy(b->d_ctr, ctr.data(), n * sizeof(int64_t), hipMemcpyHostToDevice), "upload batch tables");
-    BHIP(b, hipMemcpy(b->d_pre, pre.data(), pre.size() * sizeof(int32_t), hipMemcpyHostToDevice),
-         "upload batch tables");
+    // on the batch's stream (not the null stream: see the context's copies), then wait, since
+    // the host tables go out of scope
+    auto up = [&](void *dst, const void *src, size_t bytes) {
+      return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, b->stream);
+    };
+    BHIP(b, up(b->d_step, steps.data(), steps.size() * sizeof(pic::StepArgs)), "upload batch tables");
+    BHIP(b, up(b->d_field, fields.data(), fields.size() * sizeof(pic::FieldArgs)), "upload batch tables");
+    BHIP(b, up(b->d_par, par.data(), n * sizeof(int32_t)), "upload batch tables");
+    BHIP(b, up(b->d_ctr, ctr.data(), n * sizeof(int64_t)), "upload batch tables");
+    BHIP(b, up(b->d_pre, pre.data(), pre.size() * sizeof(int32_t)), "upload batch tables");
+    BHIP(b, hipStreamSynchronize(b->stream), "upload batch tables");
   }
   pic::BatchArgs &a = b->args;
   a.step = b->d_step;
@@ -150,11 +153,9 @@ pic_status rebuild(pic_batch *b) {
   a.pre_nodes = b->d_pre + 0 * stride;
   a.pre_cells = b->d_pre + 1 * stride;
   a.pre_scan = b->d_pre + 2 * stride;
-  a.pre_spec = b->d_pre + 3 * stride;
-  a.pre_tflag = b->d_pre + 4 * stride;
-  a.pre_one = b->d_pre + 5 * stride;
-  a.pre_tiles = b->d_pre + 6 * stride;
-  a.pre_rank = b->d_pre + 7 * stride;
+  a.pre_one = b->d_pre + 3 * stride;
+  a.pre_tiles = b->d_pre + 4 * stride;
+  a.pre_rank = b->d_pre + 5 * stride;
   pic::BatchLaunch &l = b->launch;
   l.mixed = b->precision == PIC_PREC_MIXED;
   l.ids = ids;
@@ -180,7 +181,10 @@ pic_status capture(pic_batch *b) {
     if (g) (void)hipGraphDestroy(g);
     return bhip(b, le, "graph capture");
   }
-  if (ee != hipSuccess) return bhip(b, ee, "graph capture");
+  if (ee != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return bhip(b, ee, "graph capture");
+  }
   b->graph = g;
   BHIP(b, hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0), "graph instantiate");
   return PIC_OK;
@@ -218,7 +222,7 @@ pic_status pic_batch_create(int32_t device, int32_t precision, pic_batch **out) 
   b->mem = pic::current_allocator(device);
   hipDeviceProp_t prop;
   hipError_t e = hipGetDeviceProperties(&prop, device);
-  if (e == hipSuccess) e = hipStreamCreate(&b->stream);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     g_batch_error = std::string("batch set-up: ") + hipGetErrorString(e);
     delete b;

@@ -116,6 +116,20 @@ pic_status dalloc(pic_ctx *c, T **p, size_t count, const char *what) {
   return PIC_OK;
 }
 
+// Host <-> device copies and fills run on the context's stream and the host waits for it.  The
+// null stream is not used: it would wait for every blocking stream's unrelated work, and an
+// operation on it invalidates a graph capture another thread has under way (a serving loop
+// loads new runs on one thread while it captures the batch's cycle on another).
+hipError_t copy_wait(pic_ctx *c, void *dst, const void *src, size_t bytes, hipMemcpyKind kind) {
+  const hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, c->stream);
+  return e == hipSuccess ? hipStreamSynchronize(c->stream) : e;
+}
+
+hipError_t fill_wait(pic_ctx *c, void *dst, int value, size_t bytes) {
+  const hipError_t e = hipMemsetAsync(dst, value, bytes, c->stream);
+  return e == hipSuccess ? hipStreamSynchronize(c->stream) : e;
+}
+
 // Release a block of the context (its size is known to the allocator record).
 void dfree(pic_ctx *c, void *p, size_t /*bytes*/) { c->mem.put(p); }
 
@@ -264,7 +278,7 @@ pic_status alloc_tiles(pic_ctx *c) {
   if ((st = dalloc(c, &c->mtile, (size_t)nt, "alloc deposit flags")) != PIC_OK) return st;
   // Moments deposited under another tiling may sit anywhere: every node is read (and
   // cleared) by the next field solve.
-  HIP_TRY(c, hipMemset(c->mtile, 1, (size_t)nt), "deposit flags");
+  HIP_TRY(c, fill_wait(c, c->mtile, 1, (size_t)nt), "deposit flags");
   c->tiles_alloc = nt;
   return PIC_OK;
 }
@@ -335,7 +349,7 @@ pic_status retile(pic_ctx *c) {
   for (int ss = 0; ss < c->S; ++ss) {
     if (!c->sp[ss].loaded) continue;
     ++nloaded;
-    HIP_TRY(c, hipMemcpy(csh.data(), c->sp[ss].cs[c->cur], ((size_t)nc + 1) * sizeof(int32_t),
+    HIP_TRY(c, copy_wait(c, csh.data(), c->sp[ss].cs[c->cur], ((size_t)nc + 1) * sizeof(int32_t),
                          hipMemcpyDeviceToHost), "read cell starts");
     for (int64_t cc = 0; cc < nc; ++cc)
       if (csh[cc + 1] > csh[cc]) occ[cc] = 1;
@@ -489,7 +503,7 @@ pic_status pic_init_grid(const pic_grid_desc *d, pic_ctx **out) {
     pic_destroy(c);
     return s2;
   };
-  e = hipStreamCreate(&c->own_stream);
+  e = hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking);
   if (e != hipSuccess) return bail(hip_fail(c, e, "hipStreamCreate"));
   c->stream = c->own_stream;
   const size_t nn = (size_t)g.nnodes, nc = (size_t)g.ncells;
@@ -502,18 +516,18 @@ pic_status pic_init_grid(const pic_grid_desc *d, pic_ctx **out) {
   // 8 doubles, then 8 floats
   if ((st = dalloc(c, &c->wconst64, 12, "alloc densities")) != PIC_OK) return bail(st);
   c->wconst32 = reinterpret_cast<float *>(c->wconst64 + PIC_MAX_SPECIES);
-  e = hipMemset(c->wconst64, 0, 12 * sizeof(double));
+  e = fill_wait(c, c->wconst64, 0, 12 * sizeof(double));
   if (e != hipSuccess) return bail(hip_fail(c, e, "clear densities"));
   std::vector<double> host(3 * std::max(nn, nc));
   for (int r = 0; r < 3; ++r) std::fill(host.begin() + r * nn, host.begin() + (r + 1) * nn, d->e0[r]);
-  e = hipMemcpy(c->E[0], host.data(), 3 * nn * sizeof(double), hipMemcpyHostToDevice);
+  e = copy_wait(c, c->E[0], host.data(), 3 * nn * sizeof(double), hipMemcpyHostToDevice);
   if (e != hipSuccess) return bail(hip_fail(c, e, "upload E"));
   for (int r = 0; r < 3; ++r) std::fill(host.begin() + r * nc, host.begin() + (r + 1) * nc, d->h0[r]);
-  e = hipMemcpy(c->H[0], host.data(), 3 * nc * sizeof(double), hipMemcpyHostToDevice);
+  e = copy_wait(c, c->H[0], host.data(), 3 * nc * sizeof(double), hipMemcpyHostToDevice);
   if (e != hipSuccess) return bail(hip_fail(c, e, "upload H"));
-  e = hipMemset(c->M, 0, (size_t)g.n_planes * nn * sizeof(double));
+  e = fill_wait(c, c->M, 0, (size_t)g.n_planes * nn * sizeof(double));
   if (e != hipSuccess) return bail(hip_fail(c, e, "clear moments"));
-  e = hipMemset(c->flags, 0, sizeof(uint32_t));
+  e = fill_wait(c, c->flags, 0, sizeof(uint32_t));
   if (e != hipSuccess) return bail(hip_fail(c, e, "clear flags"));
   *out = c;
   return PIC_OK;
@@ -587,19 +601,19 @@ pic_status pic_load_particles(pic_ctx *c, int32_t s, double q, double m, int64_t
     // padded: the particle kernel reads the permutation 4 entries at a time, up to 7 past
     // the last slot of a row part
     if ((rs = dalloc(c, &st.perm[b], cap + pic::kPermPad, "alloc perm")) != PIC_OK) return bail(rs);
-    if (hipMemset(st.perm[b], 0, (cap + pic::kPermPad) * sizeof(int32_t)) != hipSuccess)
+    if (fill_wait(c, st.perm[b], 0, (cap + pic::kPermPad) * sizeof(int32_t)) != hipSuccess)
       return bail(fail(c, PIC_ERR_DEVICE, "clear perm"));
     if ((rs = dalloc(c, &st.cs[b], (size_t)nc + 1, "alloc cell starts")) != PIC_OK) return bail(rs);
   }
   if ((rs = dalloc(c, &st.locode, cap, "alloc codes")) != PIC_OK) return bail(rs);
   if ((rs = dalloc(c, &st.cnt, (size_t)pic::kMoveCodes * nc, "alloc counts")) != PIC_OK) return bail(rs);
   if ((rs = dalloc(c, &st.arr, (size_t)nc, "alloc arrivals")) != PIC_OK) return bail(rs);
-  if (hipMemset(st.arr, 0, (size_t)nc * sizeof(int32_t)) != hipSuccess)
+  if (fill_wait(c, st.arr, 0, (size_t)nc * sizeof(int32_t)) != hipSuccess)
     return bail(fail(c, PIC_ERR_DEVICE, "clear arrivals"));
   if ((rs = dalloc(c, &st.bsum, (size_t)c->n_scan_blocks, "alloc scan sums")) != PIC_OK) return bail(rs);
   {
     auto up = [&](void *dst, const void *src, size_t bytes) {
-      const hipError_t e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+      const hipError_t e = copy_wait(c, dst, src, bytes, hipMemcpyHostToDevice);
       return e == hipSuccess ? PIC_OK : hip_fail(c, e, "upload particles");
     };
     const double *srcs[5] = {xi_x, xi_z, ux, uy, uz};
@@ -669,8 +683,8 @@ pic_status pic_load_fields(pic_ctx *c, const double *e, const double *h) {
     for (size_t q = 0; q < 3 * nc; ++q)
       if (!std::isfinite(h[q])) return fail(c, PIC_ERR_RANGE, "non-finite H");
   HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
-  if (e) HIP_TRY(c, hipMemcpy(c->E[c->ecur], e, 3 * nn * sizeof(double), hipMemcpyHostToDevice), "upload E");
-  if (h) HIP_TRY(c, hipMemcpy(c->H[c->hcur], h, 3 * nc * sizeof(double), hipMemcpyHostToDevice), "upload H");
+  if (e) HIP_TRY(c, copy_wait(c, c->E[c->ecur], e, 3 * nn * sizeof(double), hipMemcpyHostToDevice), "upload E");
+  if (h) HIP_TRY(c, copy_wait(c, c->H[c->hcur], h, 3 * nc * sizeof(double), hipMemcpyHostToDevice), "upload H");
   HIP_TRY(c, hipMemsetAsync(c->flags, 0, sizeof(uint32_t), c->stream), "clear flags");
   pic::batch_touch(c);
   return redeposit(c);
@@ -754,15 +768,15 @@ pic_status pic_read_moments(pic_ctx *c, double *out, int64_t len) {
   const int64_t need = (int64_t)c->g.n_planes * c->g.nnodes;
   if (!out || len < need) return fail(c, PIC_ERR_ARG, "output buffer too small");
   HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
-  HIP_TRY(c, hipMemcpy(out, c->M, (size_t)need * sizeof(double), hipMemcpyDeviceToHost), "read moments");
+  HIP_TRY(c, copy_wait(c, out, c->M, (size_t)need * sizeof(double), hipMemcpyDeviceToHost), "read moments");
   return PIC_OK;
 }
 
 pic_status pic_read_fields(pic_ctx *c, double *e, double *h) {
   if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
   HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
-  if (e) HIP_TRY(c, hipMemcpy(e, c->E[c->ecur], 3 * (size_t)c->g.nnodes * sizeof(double), hipMemcpyDeviceToHost), "read E");
-  if (h) HIP_TRY(c, hipMemcpy(h, c->H[c->hcur], 3 * (size_t)c->g.ncells * sizeof(double), hipMemcpyDeviceToHost), "read H");
+  if (e) HIP_TRY(c, copy_wait(c, e, c->E[c->ecur], 3 * (size_t)c->g.nnodes * sizeof(double), hipMemcpyDeviceToHost), "read E");
+  if (h) HIP_TRY(c, copy_wait(c, h, c->H[c->hcur], 3 * (size_t)c->g.ncells * sizeof(double), hipMemcpyDeviceToHost), "read H");
   return PIC_OK;
 }
 
@@ -770,7 +784,7 @@ static pic_status alive_count(pic_ctx *c, int s, int64_t *n) {
   *n = 0;
   if (!c->sp[s].loaded) return PIC_OK;
   int32_t v = 0;
-  HIP_TRY(c, hipMemcpy(&v, c->sp[s].cs[c->cur] + c->g.ncells, sizeof(int32_t), hipMemcpyDeviceToHost),
+  HIP_TRY(c, copy_wait(c, &v, c->sp[s].cs[c->cur] + c->g.ncells, sizeof(int32_t), hipMemcpyDeviceToHost),
           "read count");
   *n = v;
   return PIC_OK;
@@ -793,18 +807,18 @@ pic_status pic_read_particles(pic_ctx *c, int32_t s, int64_t *n_inout, double *x
   if (n == 0) return PIC_OK;
   SpeciesState &st = c->sp[s];
   std::vector<int32_t> perm((size_t)n);
-  HIP_TRY(c, hipMemcpy(perm.data(), st.perm[c->cur], (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost),
+  HIP_TRY(c, copy_wait(c, perm.data(), st.perm[c->cur], (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost),
           "read perm");
   double *outs[5] = {xi_x, xi_z, ux, uy, uz};
   if (mixed(c)) {
     // positions come back as cell index + offset, exact in FP64
     std::vector<int32_t> kc((size_t)st.cap);
     std::vector<float> tmp((size_t)st.cap);
-    HIP_TRY(c, hipMemcpy(kc.data(), st.mcell[c->cur], (size_t)st.cap * sizeof(int32_t), hipMemcpyDeviceToHost),
+    HIP_TRY(c, copy_wait(c, kc.data(), st.mcell[c->cur], (size_t)st.cap * sizeof(int32_t), hipMemcpyDeviceToHost),
             "read particles");
     for (int v = 0; v < 5; ++v) {
       if (!outs[v]) continue;
-      HIP_TRY(c, hipMemcpy(tmp.data(), st.mbuf[c->cur][v], (size_t)st.cap * sizeof(float), hipMemcpyDeviceToHost),
+      HIP_TRY(c, copy_wait(c, tmp.data(), st.mbuf[c->cur][v], (size_t)st.cap * sizeof(float), hipMemcpyDeviceToHost),
               "read particles");
       for (int64_t j = 0; j < n; ++j) {
         const int32_t loc = perm[j];
@@ -818,7 +832,7 @@ pic_status pic_read_particles(pic_ctx *c, int32_t s, int64_t *n_inout, double *x
     std::vector<double> tmp((size_t)st.cap);
     for (int v = 0; v < 5; ++v) {
       if (!outs[v]) continue;
-      HIP_TRY(c, hipMemcpy(tmp.data(), st.buf[c->cur][v], (size_t)st.cap * sizeof(double), hipMemcpyDeviceToHost),
+      HIP_TRY(c, copy_wait(c, tmp.data(), st.buf[c->cur][v], (size_t)st.cap * sizeof(double), hipMemcpyDeviceToHost),
               "read particles");
       for (int64_t j = 0; j < n; ++j) outs[v][j] = tmp[perm[j]];
     }
@@ -828,19 +842,19 @@ pic_status pic_read_particles(pic_ctx *c, int32_t s, int64_t *n_inout, double *x
       std::fill(w, w + n, st.w);
     } else if (mixed(c)) {
       std::vector<float> tw((size_t)st.cap);
-      HIP_TRY(c, hipMemcpy(tw.data(), st.mwbuf[c->cur], (size_t)st.cap * sizeof(float), hipMemcpyDeviceToHost),
+      HIP_TRY(c, copy_wait(c, tw.data(), st.mwbuf[c->cur], (size_t)st.cap * sizeof(float), hipMemcpyDeviceToHost),
               "read densities");
       for (int64_t j = 0; j < n; ++j) w[j] = (double)tw[perm[j]];
     } else {
       std::vector<double> tw((size_t)st.cap);
-      HIP_TRY(c, hipMemcpy(tw.data(), st.wbuf[c->cur], (size_t)st.cap * sizeof(double), hipMemcpyDeviceToHost),
+      HIP_TRY(c, copy_wait(c, tw.data(), st.wbuf[c->cur], (size_t)st.cap * sizeof(double), hipMemcpyDeviceToHost),
               "read densities");
       for (int64_t j = 0; j < n; ++j) w[j] = tw[perm[j]];
     }
   }
   if (id) {
     std::vector<int64_t> t2((size_t)st.cap);
-    HIP_TRY(c, hipMemcpy(t2.data(), st.ids[c->cur], (size_t)st.cap * sizeof(int64_t), hipMemcpyDeviceToHost),
+    HIP_TRY(c, copy_wait(c, t2.data(), st.ids[c->cur], (size_t)st.cap * sizeof(int64_t), hipMemcpyDeviceToHost),
             "read ids");
     for (int64_t j = 0; j < n; ++j) id[j] = t2[perm[j]];
   }
@@ -868,7 +882,7 @@ pic_status pic_get_info(pic_ctx *c, pic_info *info) {
     r.alive[s] = n;
     r.absorbed[s] = c->sp[s].loaded ? c->sp[s].n_loaded - n : 0;
   }
-  HIP_TRY(c, hipMemcpy(&r.overflow_flags, c->flags, sizeof(uint32_t), hipMemcpyDeviceToHost), "read flags");
+  HIP_TRY(c, copy_wait(c, &r.overflow_flags, c->flags, sizeof(uint32_t), hipMemcpyDeviceToHost), "read flags");
   r.device_bytes = c->mem.bytes;
   *info = r;
   return PIC_OK;
@@ -933,7 +947,7 @@ pic_status pic_energy(pic_ctx *c, double *out, int32_t len) {
   hipError_t e = hipMemsetAsync(d, 0, (1 + (size_t)c->S) * sizeof(double), c->stream);
   if (e == hipSuccess) e = pic::launch_energy(a, c->E[c->ecur], c->H[c->hcur], d, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  if (e == hipSuccess) e = hipMemcpy(out, d, (1 + (size_t)c->S) * sizeof(double), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = copy_wait(c, out, d, (1 + (size_t)c->S) * sizeof(double), hipMemcpyDeviceToHost);
   dfree(c, d, (1 + (size_t)c->S) * sizeof(double));
   if (e != hipSuccess) return hip_fail(c, e, "energy");
   return PIC_OK;

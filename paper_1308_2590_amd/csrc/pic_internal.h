@@ -108,6 +108,7 @@ struct FieldArgs {
   // read only where the flag of the tile holding the node is set; the H update clears the
   // flags for the next deposit.  NULL: every node is read and cleared.
   uint8_t *mtile;
+  uint8_t *tact_next;        // batched cycle: the next order's tile flags, cleared here (or NULL)
   int32_t tx, tz, ntx;
   double r2dx, r2dz;         // 1 / (2 dx), 1 / (2 dz) of the centred differences
 };
@@ -125,9 +126,7 @@ struct BatchArgs {
   // exclusive prefix sums over runs ([nruns + 1]) of the work items of each kernel
   const int32_t *pre_nodes;  // blocks of kSolveNodes * kBlock nodes
   const int32_t *pre_cells;  // blocks of kHCells * kBlock cells
-  const int32_t *pre_scan;   // scan blocks x species slots
-  const int32_t *pre_spec;   // species slots
-  const int32_t *pre_tflag;  // blocks of kBlock tiles
+  const int32_t *pre_scan;   // scan blocks x species slots (both passes of the sort's scan)
   const int32_t *pre_one;    // one item per run
   int32_t *pre_tiles;        // active tiles of the current order (written each cycle)
   int32_t *pre_rank;         // active tiles x species slots (written each cycle)

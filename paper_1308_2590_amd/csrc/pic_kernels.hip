@@ -21,7 +21,7 @@
 //               offsets (per block, then the block totals added), the tiles holding particles
 //               in the next order as flags and, from one extra block, as an ordered list;
 //   k_tile_flags / k_tile_compact  the same flags and list from cell starts (after loads);
-//   kb_scan_* / kb_tile_*  three-pass scan and separate tile passes of batched runs;
+//   kb_scan1 / kb_scan2  the same two passes for every run of a batch;
 //   k_rank      stable destination of every particle: cell start + particles arriving from
 //               source cells with a smaller key + rank within (source cell, move code),
 //               written as the next cycle's slot -> location permutation.
@@ -341,7 +341,11 @@ __device__ __forceinline__ void update_h_body(const FieldArgs &a, int64_t c0, in
     a.H_new[2 * nc + c] = hn[q][2];
     // The E solve has read the deposit flags: clear them for the next deposit (there are no
     // more tiles than cells).
-    if (a.mtile && c < (int64_t)a.ntx * ((g.nz + a.tz - 1) / a.tz)) a.mtile[c] = 0;
+    if (c < (int64_t)a.ntx * ((g.nz + a.tz - 1) / a.tz)) {
+      if (a.mtile) a.mtile[c] = 0;
+      // the next order's tile flags, set again by the sort's scan (batched cycle)
+      if (a.tact_next) a.tact_next[c] = 0;
+    }
   }
 }
 
@@ -1231,12 +1235,6 @@ void k_particles(const StepArgs a) {
 // Sort
 // ------------------------------------------------------------------------------------------
 
-// Tile index of the cell (is, ks) (tiles are row-major, tx x tz cells; the last tile of a row
-// or column may be partial).
-__device__ __forceinline__ int cell_tile(const TileArgs &t, int is, int ks) {
-  return (ks / t.tz) * t.ntx + is / t.tx;
-}
-
 __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
@@ -1260,64 +1258,6 @@ __device__ int block_excl_scan(int v, int *sh, int *total) {
   __syncthreads();
   *total = tot;
   return off + inc - v;
-}
-
-__device__ __forceinline__ void scan_counts_body(const StepArgs &a, int bx, int s) {
-  __shared__ int sh[kBlock / 64];
-  const SpeciesArgs &sp = a.sp[s];
-  if (!sp.active) return;
-  const GridArgs &g = a.g;
-  const int64_t c0 = (int64_t)bx * kScanBlock + (int64_t)threadIdx.x * kScanItems;
-  int in[kScanItems];
-  int sum = 0;
-  // particles arriving in each cell (added by the particle kernel), cleared for the next cycle
-#pragma unroll
-  for (int q = 0; q < kScanItems; ++q) {
-    const int64_t c = c0 + q;
-    int v = 0;
-    if (c < g.ncells) {
-      v = sp.arr[c];
-      if (v) sp.arr[c] = 0;
-    }
-    in[q] = v;
-    sum += v;
-  }
-  int total;
-  int off = block_excl_scan(sum, sh, &total);
-#pragma unroll
-  for (int q = 0; q < kScanItems; ++q) {
-    const int64_t c = c0 + q;
-    if (c < g.ncells) sp.cs_new[c] = off;
-    off += in[q];
-  }
-  if (threadIdx.x == 0) sp.bsum[bx] = total;
-}
-
-__device__ __forceinline__ void scan_blocks_body(const StepArgs &a, int s, int nblocks) {
-  __shared__ int sh[1024 / 64];
-  const SpeciesArgs &sp = a.sp[s];
-  if (!sp.active) return;
-  int carry = 0;
-  for (int base = 0; base < nblocks; base += blockDim.x) {
-    const int b = base + threadIdx.x;
-    const int v = b < nblocks ? sp.bsum[b] : 0;
-    int total;
-    const int off = block_excl_scan(v, sh, &total);
-    if (b < nblocks) sp.bsum[b] = carry + off;
-    carry += total;
-  }
-  if (threadIdx.x == 0) sp.cs_new[a.g.ncells] = carry;
-}
-
-__device__ __forceinline__ void scan_finish_body(const StepArgs &a, int bx, int s) {
-  const SpeciesArgs &sp = a.sp[s];
-  if (!sp.active) return;
-  const int add = sp.bsum[bx];
-  const int64_t c0 = (int64_t)bx * kScanBlock;
-  for (int q = threadIdx.x; q < kScanBlock; q += blockDim.x) {
-    const int64_t c = c0 + q;
-    if (c < a.g.ncells) sp.cs_new[c] += add;
-  }
 }
 
 // Stable destinations of one tile's particles.  The destination base of every (cell, move
@@ -1625,9 +1565,8 @@ __global__ __launch_bounds__(1024) void k_tile_compact(const StepArgs a) { tile_
 // tile flags (a tile is active when particles arrive in one of its cells; the particle kernel
 // of the cycle cleared the flags).  Pass 2 (k_scan_apply): every block adds the totals of the
 // blocks before it; one extra block compacts the tile flags into the ordered tile list.
-__global__ __launch_bounds__(kBlock) void k_scan_counts(const StepArgs a) {
+__device__ __forceinline__ void scan1_body(const StepArgs &a, int bx, int s) {
   __shared__ int sh[kBlock / 64];
-  const int s = blockIdx.y, bx = blockIdx.x;
   const SpeciesArgs &sp = a.sp[s];
   if (!sp.active) return;
   const GridArgs &g = a.g;
@@ -1699,14 +1638,14 @@ __global__ __launch_bounds__(kBlock) void k_scan_counts(const StepArgs a) {
   if (threadIdx.x == 0) sp.bsum[bx] = total;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_apply(const StepArgs a) {
+__global__ __launch_bounds__(kBlock) void k_scan_counts(const StepArgs a) {
+  scan1_body(a, blockIdx.x, blockIdx.y);
+}
+
+// Pass 2 for block bx of species s (bx < n_scan1_blocks).
+__device__ __forceinline__ void scan2_body(const StepArgs &a, int bx, int s) {
   __shared__ int sh[kBlock / 64];
-  const int s = blockIdx.y, bx = blockIdx.x;
   const int nb = a.n_scan1_blocks;
-  if (bx == nb) {
-    if (s == 0) tile_compact_body(a);
-    return;
-  }
   const SpeciesArgs &sp = a.sp[s];
   if (!sp.active) return;
   int part = 0;
@@ -1731,6 +1670,15 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const StepArgs a) {
       if (c0 + q < g.ncells) sp.cs_new[c0 + q] += prefix;
   }
   if (bx == nb - 1 && threadIdx.x == 0) sp.cs_new[g.ncells] = prefix + sp.bsum[bx];
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_apply(const StepArgs a) {
+  const int s = blockIdx.y, bx = blockIdx.x;
+  if (bx == a.n_scan1_blocks) {
+    if (s == 0) tile_compact_body(a);
+    return;
+  }
+  scan2_body(a, bx, s);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1824,50 +1772,34 @@ void kb_particles(const BatchArgs b) {
   }
 }
 
-__global__ __launch_bounds__(kBlock) void kb_scan_counts(const BatchArgs b) {
+// The two-pass scan of every run's sort, as in a single run: pass 1 over (run, species, block
+// of cells) items; pass 2 over the same items, then one tile-list compaction item per run.
+// The next order's tile flags were cleared by the H update of the cycle.
+__global__ __launch_bounds__(kBlock) void kb_scan1(const BatchArgs b) {
   const int total = b.pre_scan[b.nruns];
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
     const int r = find_run(b.pre_scan, b.nruns, w);
     const StepArgs &sa = run_step(b, r);
     const int li = w - b.pre_scan[r];
-    const int s = li / sa.n_scan_blocks;
-    scan_counts_body(sa, li - s * sa.n_scan_blocks, s);
+    const int s = li / sa.n_scan1_blocks;
+    scan1_body(sa, li - s * sa.n_scan1_blocks, s);
     __syncthreads();
   }
 }
 
-__global__ __launch_bounds__(1024) void kb_scan_blocks(const BatchArgs b) {
-  const int total = b.pre_spec[b.nruns];
+__global__ __launch_bounds__(kBlock) void kb_scan2(const BatchArgs b) {
+  const int nscan = b.pre_scan[b.nruns];
+  const int total = nscan + b.nruns;
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
-    const int r = find_run(b.pre_spec, b.nruns, w);
-    const StepArgs &sa = run_step(b, r);
-    scan_blocks_body(sa, w - b.pre_spec[r], sa.n_scan_blocks);
-    __syncthreads();
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void kb_scan_finish(const BatchArgs b) {
-  const int total = b.pre_scan[b.nruns];
-  for (int w = blockIdx.x; w < total; w += gridDim.x) {
-    const int r = find_run(b.pre_scan, b.nruns, w);
-    const StepArgs &sa = run_step(b, r);
-    const int li = w - b.pre_scan[r];
-    const int s = li / sa.n_scan_blocks;
-    scan_finish_body(sa, li - s * sa.n_scan_blocks, s);
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void kb_tile_flags(const BatchArgs b) {
-  const int total = b.pre_tflag[b.nruns];
-  for (int w = blockIdx.x; w < total; w += gridDim.x) {
-    const int r = find_run(b.pre_tflag, b.nruns, w);
-    tile_flags_body(run_step(b, r), (w - b.pre_tflag[r]) * kBlock + threadIdx.x, 1);
-  }
-}
-
-__global__ __launch_bounds__(1024) void kb_tile_compact(const BatchArgs b) {
-  for (int r = blockIdx.x; r < b.nruns; r += gridDim.x) {
-    tile_compact_body(run_step(b, r));
+    if (w >= nscan) {
+      tile_compact_body(run_step(b, w - nscan));
+    } else {
+      const int r = find_run(b.pre_scan, b.nruns, w);
+      const StepArgs &sa = run_step(b, r);
+      const int li = w - b.pre_scan[r];
+      const int s = li / sa.n_scan1_blocks;
+      scan2_body(sa, li - s * sa.n_scan1_blocks, s);
+    }
     __syncthreads();
   }
 }
@@ -1989,11 +1921,8 @@ hipError_t launch_batch_cycle(const BatchArgs &b, const BatchLaunch &l, hipStrea
   hipLaunchKernelGGL(kb_prefix, dim3(1), dim3(1024), 0, s, b);
   const dim3 gp((unsigned)l.grid_particles);
   hipLaunchKernelGGL(batch_particles_kernel(l.mixed, l.ids, l.pw), gp, blk, l.lds_particles, s, b);
-  hipLaunchKernelGGL(kb_scan_counts, small, blk, 0, s, b);
-  hipLaunchKernelGGL(kb_scan_blocks, small, dim3(1024), 0, s, b);
-  hipLaunchKernelGGL(kb_scan_finish, small, blk, 0, s, b);
-  hipLaunchKernelGGL(kb_tile_flags, small, blk, 0, s, b);
-  hipLaunchKernelGGL(kb_tile_compact, small, dim3(1024), 0, s, b);
+  hipLaunchKernelGGL(kb_scan1, small, blk, 0, s, b);
+  hipLaunchKernelGGL(kb_scan2, small, blk, 0, s, b);
   hipLaunchKernelGGL(kb_rank, dim3((unsigned)l.grid_rank), blk, l.lds_rank, s, b);
   hipLaunchKernelGGL(kb_end, dim3((unsigned)((b.nruns + kBlock - 1) / kBlock)), blk, 0, s, b);
   return hipGetLastError();
