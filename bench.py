@@ -71,6 +71,11 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_PARTICLE = {"fp64": 80, "mixed": 48}
 
 
+# the sort's ranker (pic_set_rank_mode): automatic unless --rank says otherwise
+RANK_MODE = 0
+RANK_NAMES = {0: "auto", 1: "rows", 2: "cells"}
+
+
 def bytes_per_node(S):
     return 72 + 8 * (12 + S)
 
@@ -89,6 +94,8 @@ def parse():
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: time candidate tile shapes during warmup and keep the fastest")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--rank", choices=["auto", "rows", "cells"], default="auto",
+                    help="ranker of the cell sort: automatic, tile rows, or one thread per cell")
     ap.add_argument("--compare-steps", type=int, default=20,
                     help="timed cycles of each FP64 / mixed comparison run (0 skips them)")
     ap.add_argument("--drift-steps", type=int, default=500,
@@ -203,6 +210,7 @@ def run_gpu(binding, torch, wl, precision, steps, warmup, tile, autotune=False):
     ctx = binding.Context(wl.grid, track_ids=False, tile=tile, precision=prec)
     for s, sp in enumerate(wl.species):
         ctx.load_particles(s, sp.q, sp.m, sp.w, sp.xi_x, sp.xi_z, sp.ux, sp.uy, sp.uz)
+    ctx.set_rank_mode(RANK_MODE)
     tuned = None
     if autotune:
         from paper_1308_2590_amd import autotune as at
@@ -249,6 +257,7 @@ def run_gpu(binding, torch, wl, precision, steps, warmup, tile, autotune=False):
         "ms_per_step": 1e3 * wall / steps,
         "particles": int(n_alive0),
         "tile": list(info1["tile"]),
+        "rank": RANK_NAMES[info1["rank_mode"]],
         "part_ms": part_ms,
         "alg_bytes": alg_bytes,
         "alg_bytes_touched": alg_bytes_touched,
@@ -492,6 +501,8 @@ def serving(args):
 
 def main():
     args = parse()
+    global RANK_MODE
+    RANK_MODE = {"auto": 0, "rows": 1, "cells": 2}[args.rank]
     if args.cpu_worker:
         # child of cpu_baseline: one copy of the oracle on its sample, no GPU
         ps, el, steps = cpu_run(args.cpu_worker, args.cpu_seconds)
@@ -539,6 +550,7 @@ def main():
             "species": S,
             "precision": args.precision,
             "tile": m["tile"],
+            "rank": m["rank"],
             "note": wl.note,
         },
         "roofline": roofline(m, args.workload, args.precision),

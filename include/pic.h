@@ -67,6 +67,8 @@ typedef enum {
 
 enum { PIC_BC_PERIODIC = 0, PIC_BC_ABSORBING = 1 };
 enum { PIC_PREC_FP64 = 0, PIC_PREC_MIXED = 1 };
+/* How the cell sort finds each particle's slot in the next order (pic_set_rank_mode). */
+enum { PIC_RANK_AUTO = 0, PIC_RANK_ROWS = 1, PIC_RANK_CELLS = 2 };
 
 /* Mover options (bits of pic_set_mover's argument), two readings of what the paper leaves
  * open, for comparing their energy behaviour:
@@ -113,6 +115,7 @@ typedef struct {
   int64_t alive[PIC_MAX_SPECIES];     /* particles held per species */
   int64_t absorbed[PIC_MAX_SPECIES];  /* particles removed at absorbing boundaries */
   uint32_t overflow_flags;   /* PIC_FLAG_* raised since the last pic_load_* call */
+  int32_t rank_mode;         /* PIC_RANK_ROWS or PIC_RANK_CELLS: the ranker the sort uses */
   int64_t device_bytes;      /* device memory held by the context */
 } pic_info;
 
@@ -162,6 +165,15 @@ pic_status pic_load_fields(pic_ctx *ctx, const double *e, const double *h);
  * the old shape is kept),
  * PIC_ERR_STATE (no particles loaded). */
 pic_status pic_set_tiles(pic_ctx *ctx, int32_t tile_x, int32_t tile_z);
+
+/* Choose how the cell sort ranks the particles (the result is the same stable order either
+ * way).  PIC_RANK_ROWS: per tile, the destination of every (cell, move code) is staged in LDS
+ * and one wavefront per tile row ranks 64 slots at a time with ballots (many particles per
+ * cell).  PIC_RANK_CELLS: one thread per cell computes its destinations from its neighbours'
+ * counts and walks its own slots (few particles per cell).  PIC_RANK_AUTO (the default)
+ * picks by the particles per occupied cell at the last load or re-tiling.
+ * Errors: PIC_ERR_ARG for another mode. */
+pic_status pic_set_rank_mode(pic_ctx *ctx, int32_t mode);
 
 /* Set the cycle counter and time t = step * dt (used by the x = 0 source). */
 pic_status pic_set_step(pic_ctx *ctx, int64_t step);

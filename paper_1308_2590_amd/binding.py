@@ -21,8 +21,9 @@ STATUS = {0: "PIC_OK", 1: "PIC_ERR_ARG", 2: "PIC_ERR_OOM", 3: "PIC_ERR_DEVICE",
 MAX_SPECIES = 8
 MOVER_GAMMA_PREDICT = 1   # gamma-bar = gamma(u^n + beta E^n) (Boris-style predictor)
 MOVER_B_BILINEAR = 2      # B interpolated from the four surrounding cell centres
+RANK_AUTO, RANK_ROWS, RANK_CELLS = 0, 1, 2   # rankers of the cell sort (pic_set_rank_mode)
 EXPORTED = ["pic_init_grid", "pic_load_particles", "pic_load_fields", "pic_set_tiles",
-            "pic_set_step", "pic_step",
+            "pic_set_rank_mode", "pic_set_step", "pic_step",
             "pic_read_moments", "pic_read_fields", "pic_read_particles", "pic_get_info",
             "pic_set_stream", "pic_sync", "pic_profile_enable", "pic_profile_read",
             "pic_set_mover", "pic_energy", "pic_energy_noalloc", "pic_set_allocator",
@@ -57,7 +58,7 @@ class Info(C.Structure):
                 ("cells_z", C.c_int32), ("tile_x", C.c_int32), ("tile_z", C.c_int32),
                 ("precision", C.c_int32), ("alive", C.c_int64 * MAX_SPECIES),
                 ("absorbed", C.c_int64 * MAX_SPECIES), ("overflow_flags", C.c_uint32),
-                ("device_bytes", C.c_int64)]
+                ("rank_mode", C.c_int32), ("device_bytes", C.c_int64)]
 
 
 class Profile(C.Structure):
@@ -93,6 +94,7 @@ def load_library(path: str = LIB_PATH):
         "pic_load_particles": ([P, I32, D, D, I64, P, P, P, P, P, P, D], C.c_int),
         "pic_load_fields": ([P, P, P], C.c_int),
         "pic_set_tiles": ([P, I32, I32], C.c_int),
+        "pic_set_rank_mode": ([P, I32], C.c_int),
         "pic_set_step": ([P, I64], C.c_int),
         "pic_step": ([P, I32], C.c_int),
         "pic_read_moments": ([P, P, I64], C.c_int),
@@ -222,6 +224,10 @@ class Context:
     def set_tiles(self, tile_x, tile_z):
         self._check(self.lib.pic_set_tiles(self.h, int(tile_x), int(tile_z)))
 
+    def set_rank_mode(self, mode):
+        """RANK_AUTO, RANK_ROWS or RANK_CELLS (the sort's ranker; same order either way)."""
+        self._check(self.lib.pic_set_rank_mode(self.h, int(mode)))
+
     def set_mover(self, options):
         """MOVER_* bits (0: the default mover); FP64 contexts only."""
         self._check(self.lib.pic_set_mover(self.h, int(options)))
@@ -279,7 +285,8 @@ class Context:
                 "tile": (inf.tile_x, inf.tile_z), "precision": inf.precision,
                 "alive": [inf.alive[s] for s in range(S)],
                 "absorbed": [inf.absorbed[s] for s in range(S)],
-                "overflow_flags": inf.overflow_flags, "device_bytes": inf.device_bytes}
+                "overflow_flags": inf.overflow_flags, "rank_mode": inf.rank_mode,
+                "device_bytes": inf.device_bytes}
 
     def set_stream(self, stream=None):
         """stream: a torch.cuda.Stream, a raw hipStream_t as int, or None (own stream)."""

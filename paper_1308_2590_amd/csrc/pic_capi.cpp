@@ -190,11 +190,22 @@ void choose_tiles(pic_ctx *c, int64_t total, int64_t occupied, int nspecies) {
   c->tiles.per_xcd = (c->tiles.ntiles + 7) / 8;
 }
 
+// The sort's ranker: one thread per cell up to this many particles per occupied cell and
+// species, the row walk above.
+constexpr double kRankCellsMaxPerCell = 16.0;
+
+bool rank_cells(const pic_ctx *c) {
+  if (c->rank_mode == PIC_RANK_CELLS) return true;
+  if (c->rank_mode == PIC_RANK_ROWS) return false;
+  return c->rank_cells_auto;
+}
+
 pic::StepArgs step_args(pic_ctx *c, bool push) {
   pic::StepArgs a{};
   a.g = c->g;
   a.t = c->tiles;
   a.mixed = mixed(c) ? 1 : 0;
+  a.rank_cells = rank_cells(c) ? 1 : 0;
   a.n_scan_blocks = c->n_scan_blocks;
   a.n_scan1_blocks = c->n_scan1_blocks;
   a.nsp = c->S;
@@ -358,6 +369,8 @@ pic_status retile(pic_ctx *c) {
   int64_t occupied = 0;
   for (uint8_t o : occ) occupied += o;
   choose_tiles(c, total, occupied, nloaded);
+  c->rank_cells_auto = occupied > 0 && nloaded > 0 &&
+                       (double)total / ((double)occupied * nloaded) <= kRankCellsMaxPerCell;
   if (pic::particle_lds_bytes(c->g, c->tiles, mixed(c), any_pw(c)) > c->lds_max)
     return fail(c, PIC_ERR_ARG, "tile too large: its LDS accumulators exceed the LDS of a block");
   return PIC_OK;
@@ -715,6 +728,15 @@ pic_status pic_set_tiles(pic_ctx *c, int32_t tile_x, int32_t tile_z) {
   return PIC_OK;
 }
 
+pic_status pic_set_rank_mode(pic_ctx *c, int32_t mode) {
+  if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
+  if (mode != PIC_RANK_AUTO && mode != PIC_RANK_ROWS && mode != PIC_RANK_CELLS)
+    return fail(c, PIC_ERR_ARG, "mode must be PIC_RANK_AUTO, PIC_RANK_ROWS or PIC_RANK_CELLS");
+  c->rank_mode = mode;
+  pic::batch_touch(c);
+  return PIC_OK;
+}
+
 pic_status pic_set_step(pic_ctx *c, int64_t step) {
   if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
   if (step < 0) return fail(c, PIC_ERR_ARG, "step must be >= 0");
@@ -883,6 +905,7 @@ pic_status pic_get_info(pic_ctx *c, pic_info *info) {
     r.absorbed[s] = c->sp[s].loaded ? c->sp[s].n_loaded - n : 0;
   }
   HIP_TRY(c, copy_wait(c, &r.overflow_flags, c->flags, sizeof(uint32_t), hipMemcpyDeviceToHost), "read flags");
+  r.rank_mode = rank_cells(c) ? PIC_RANK_CELLS : PIC_RANK_ROWS;
   r.device_bytes = c->mem.bytes;
   *info = r;
   return PIC_OK;

@@ -82,6 +82,8 @@ struct pic_ctx {
   int64_t step = 0;
   size_t lds_max = 65536;  // LDS a block may use on the context's device
   int32_t mover = 0;       // PIC_MOVER_* options; 0: the tile kernel's default mover
+  int32_t rank_mode = PIC_RANK_AUTO;
+  bool rank_cells_auto = false;  // the automatic choice, made with the tile shape
   int32_t n_scan_blocks = 0;
   int32_t n_scan1_blocks = 0;  // blocks of the scan of a cycle's sort
   std::string err;

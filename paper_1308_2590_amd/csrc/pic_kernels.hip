@@ -1472,6 +1472,159 @@ __device__ __forceinline__ void rank_body(const StepArgs &a, int tile, int speci
   }
 }
 
+// Stable destinations with one thread per cell of an active tile (one species per block,
+// wavefronts over runs of 64 cells).  A cell's particles that move with code d go, in the
+// next order, to the start of the destination cell, plus the particles arriving there from
+// source cells with a smaller key, plus their rank among the cell's earlier slots with code d.
+// The thread computes that first slot for each code its cell uses, from the destination's
+// next-order start and the counts of the destination's sources (read only for a source that
+// holds particles in the current order: the counts of a cell without particles may be left
+// from an earlier cycle), then walks its cell's slots in order.  Move codes are canonical
+// after the wrap (one code per source and destination pair), so on grids one or two cells
+// wide a source listed under two codes has a zero count under the other.  No LDS and no
+// cross-lane work: for few particles per cell the row walk's per-tile staging costs more.
+__device__ __forceinline__ void rank_cells_body(const StepArgs &a, int tile, int species) {
+  const GridArgs &g = a.g;
+  const TileArgs &t = a.t;
+  const SpeciesArgs &sp = a.sp[species];
+  if (!sp.active) return;
+  const int tzi = tile / t.ntx, txi = tile - tzi * t.ntx;
+  const int i0 = txi * t.tx, k0 = tzi * t.tz;
+  const int cw = min(i0 + t.tx, g.nx) - i0, ch = min(k0 + t.tz, g.nz) - k0;
+  const int ncell = cw * ch;
+  const int total = sp.cs_new[g.ncells];
+  const bool periodic_x = g.bc_x == PIC_BC_PERIODIC;
+  const SmallDiv div_cw(cw);
+  for (int e = threadIdx.x; e < ncell; e += blockDim.x) {
+    const int lk = div_cw.q(e), li = e - lk * cw;
+    const int ci = i0 + li, ck = k0 + lk;
+    const int c = ck * g.nx + ci;
+    // Issued together: the cell's slot range and counts, its own next-order start, and the
+    // counts of the sources that precede it among the sources of its own cell as a destination
+    // (code 4, the particles that stay): in key order these are the row below and the left
+    // neighbour (codes 5 to 8); codes 0 to 3 come before it only through a wrap.
+    const int cb = sp.cs[c], ce = sp.cs[c + 1];
+    int cur[kMoveCodes];
+#pragma unroll
+    for (int d = 0; d < kMoveCodes; ++d) cur[d] = sp.cnt[(int64_t)d * g.ncells + c];
+    int stay = sp.cs_new[c];
+    int pv[4], pb[4], pe[4];
+    bool pm[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int d2 = 5 + q;
+      int si = ci - (d2 % 3 - 1), sk = ck - (d2 / 3 - 1);
+      bool in = true;
+      if (periodic_x) {
+        if (si < 0) si += g.nx;
+        if (si >= g.nx) si -= g.nx;
+      } else {
+        in = si >= 0 && si < g.nx;
+      }
+      if (sk < 0) sk += g.nz;
+      const int sc = in ? sk * g.nx + si : c;
+      pm[q] = in && sc < c;
+      pb[q] = sp.cs[sc];
+      pe[q] = sp.cs[sc + 1];
+      pv[q] = sp.cnt[(int64_t)d2 * g.ncells + sc];
+    }
+    if (cb >= ce) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (pm[q] && pe[q] > pb[q]) stay += pv[q];
+    if (ck == g.nz - 1 || (periodic_x && ci == g.nx - 1)) {
+#pragma unroll
+      for (int d2 = 0; d2 < 4; ++d2) {
+        int si = ci - (d2 % 3 - 1), sk = ck - (d2 / 3 - 1);
+        bool in = true;
+        if (periodic_x) {
+          if (si < 0) si += g.nx;
+          if (si >= g.nx) si -= g.nx;
+        } else {
+          in = si >= 0 && si < g.nx;
+        }
+        if (sk >= g.nz) sk -= g.nz;
+        const int sc = sk * g.nx + si;
+        if (in && sc < c) {
+          const int sb = sp.cs[sc], se = sp.cs[sc + 1];
+          const int v = sp.cnt[(int64_t)d2 * g.ncells + sc];
+          if (se > sb) stay += v;
+        }
+      }
+    }
+    // the other codes a cell uses (particles that change cell: few per cycle)
+#pragma unroll
+    for (int d = 0; d < kMoveCodes; ++d) {
+      if (d == 4) {
+        cur[d] = stay;
+        continue;
+      }
+      if (cur[d] <= 0) continue;
+      // destination (inside the grid: an absorbed particle has its own code)
+      int di = ci + (d % 3 - 1), dk = ck + (d / 3 - 1);
+      if (di < 0) di += g.nx;
+      if (di >= g.nx) di -= g.nx;
+      if (dk < 0) dk += g.nz;
+      if (dk >= g.nz) dk -= g.nz;
+      const int dc = dk * g.nx + di;
+      int b = sp.cs_new[dc];
+#pragma unroll
+      for (int d2 = 0; d2 < kMoveCodes; ++d2) {
+        // the source that sends code d2 to the destination
+        int si = di - (d2 % 3 - 1), sk = dk - (d2 / 3 - 1);
+        bool in = true;
+        if (periodic_x) {
+          if (si < 0) si += g.nx;
+          if (si >= g.nx) si -= g.nx;
+        } else {
+          in = si >= 0 && si < g.nx;
+        }
+        if (sk < 0) sk += g.nz;
+        if (sk >= g.nz) sk -= g.nz;
+        const int sc = sk * g.nx + si;
+        if (in && sc < c) {
+          const int sb = sp.cs[sc], se = sp.cs[sc + 1];
+          const int v = sp.cnt[(int64_t)d2 * g.ncells + sc];
+          if (se > sb) b += v;
+        }
+      }
+      cur[d] = b;
+    }
+    // the cell's slots in order, four move codes loaded at a time
+    for (int j = cb; j < ce; j += 4) {
+      uint32_t lc[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) lc[q] = sp.locode[min(j + q, ce - 1)];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (j + q >= ce) break;
+        const int d = (int)(lc[q] & 15u);
+        int slot = -1;
+#pragma unroll
+        for (int dd = 0; dd < kMoveCodes; ++dd) {
+          if (d == dd) {
+            slot = cur[dd];
+            cur[dd] = slot + 1;
+          }
+        }
+        if (d < kMoveCodes) {
+          if (slot >= 0 && slot < total) {
+            sp.perm_new[slot] = (int)(lc[q] >> 4);
+          } else {
+            atomicOr(a.flags, kFlagSlot);
+          }
+        }
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_rank_cells(const StepArgs a) {
+  const int tile = block_tile(a.t, a.tile_list);
+  if (tile < 0) return;
+  rank_cells_body(a, tile, blockIdx.y);
+}
+
 __global__ __launch_bounds__(kBlock) void k_rank(const StepArgs a) {
   const int tile = block_tile(a.t, a.tile_list);
   if (tile < 0) return;
@@ -1811,7 +1964,10 @@ __global__ __launch_bounds__(kBlock) void kb_rank(const BatchArgs b) {
     const StepArgs &sa = run_step(b, r);
     const int li = w - b.pre_rank[r];
     const int idx = li / sa.nsp;
-    rank_body(sa, sa.tile_list[idx], li - idx * sa.nsp);
+    if (sa.rank_cells)
+      rank_cells_body(sa, sa.tile_list[idx], li - idx * sa.nsp);
+    else
+      rank_body(sa, sa.tile_list[idx], li - idx * sa.nsp);
     __syncthreads();
   }
 }
@@ -1890,8 +2046,16 @@ hipError_t launch_sort(const StepArgs &a, hipStream_t s) {
                      s, a);
   hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)a.n_scan1_blocks + 1u, (unsigned)a.nsp), dim3(kBlock),
                      0, s, a);
-  hipLaunchKernelGGL(k_rank, dim3(8u * (unsigned)a.t.per_xcd, (unsigned)a.nsp), dim3(kBlock),
-                     rank_lds_bytes(a.t), s, a);
+  const dim3 grid(8u * (unsigned)a.t.per_xcd, (unsigned)a.nsp);
+  if (a.rank_cells) {
+    // one thread per cell of a tile, at most a full block
+    const int cells = a.t.tx * a.t.tz;
+    const int rounded = (cells + 63) / 64 * 64;
+    const unsigned threads = (unsigned)(rounded < kBlock ? rounded : kBlock);
+    hipLaunchKernelGGL(k_rank_cells, grid, dim3(threads), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(k_rank, grid, dim3(kBlock), rank_lds_bytes(a.t), s, a);
+  }
   return hipGetLastError();
 }
 

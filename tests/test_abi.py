@@ -132,3 +132,9 @@ def test_load_particles_argument_errors_without_device():
     """pic_load_particles refuses a NULL context before touching a device."""
     lib = binding.load_library()
     assert lib.pic_load_particles(None, 0, -1.0, 1.0, 0, None, None, None, None, None, None, 1.0) == 1
+
+
+def test_rank_mode_argument_errors_without_device():
+    lib = binding.load_library()
+    assert lib.pic_set_rank_mode(None, binding.RANK_CELLS) == 1
+    assert b"NULL" in lib.pic_last_error(None)

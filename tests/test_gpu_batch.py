@@ -89,6 +89,10 @@ def test_batch_matches_solo_fp64(pic, graph):
     _say(f"batch fp64 graph={graph}")
     solo = [make(pic, wl, 0, i) for i, wl in enumerate(wls)]
     mem = [make(pic, wl, 0, i) for i, wl in enumerate(wls)]
+    # both rankers of the sort, in the batch and alone (the order is the same)
+    for i in range(len(wls)):
+        mem[i].set_rank_mode(1 + i % 2)
+        solo[i].set_rank_mode(2 - i % 2)
     b = pic.Batch(0, 0)
     b.set_graph(graph)
     for c in mem:

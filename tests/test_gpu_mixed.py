@@ -250,13 +250,15 @@ def compare_step_unlabelled(ctx, orc, wl):
     return n_face
 
 
+@pytest.mark.parametrize("rank", [1, 2])
 @pytest.mark.parametrize("tile", [(0, 0), (4, 4), (8, 2)])
 @pytest.mark.parametrize("wi", range(len(SMALL)))
-def test_mixed_one_step(pic, wi, tile):
+def test_mixed_one_step(pic, wi, tile, rank):
     wl = SMALL[wi]
-    _say(f"mixed step {wl.name} tile={tile}")
+    _say(f"mixed step {wl.name} tile={tile} rank={rank}")
     fields = picgen.random_fields(100 + wi, wl.grid)
     ctx, orc = setup_both(pic, wl, fields=fields, tile=tile)
+    ctx.set_rank_mode(rank)
     prev = [ctx.read_particles(s, ids=True)["id"] for s in range(len(wl.species))]
     ctx.step(1)
     orc.step(1)

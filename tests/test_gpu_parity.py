@@ -153,13 +153,18 @@ def test_load_sort_and_deposit(pic, wi, tile):
     ctx.close()
 
 
+@pytest.mark.parametrize("rank", [1, 2])
 @pytest.mark.parametrize("tile", [(0, 0), (4, 4), (8, 2)])
 @pytest.mark.parametrize("wi", range(len(SMALL)))
-def test_steps_from_identical_state(pic, wi, tile):
+def test_steps_from_identical_state(pic, wi, tile, rank):
+    """Three cycles from the same state, with either ranker of the sort (tile rows, or one
+    thread per cell)."""
     wl = SMALL[wi]
-    _say(f"steps {wl.name} tile={tile}")
+    _say(f"steps {wl.name} tile={tile} rank={rank}")
     fields = picgen.random_fields(100 + wi, wl.grid, amp_e=0.05, amp_h=0.2)
     ctx, orc = setup_both(pic, wl, fields=fields, tile=tile)
+    ctx.set_rank_mode(rank)
+    assert ctx.get_info()["rank_mode"] == rank
     for _ in range(3):
         ctx.step(1)
         orc.step(1)
@@ -172,14 +177,16 @@ def test_steps_from_identical_state(pic, wi, tile):
     ctx.close()
 
 
+@pytest.mark.parametrize("rank", [1, 2])
 @pytest.mark.parametrize("wi", [0, 1, 3])
-def test_steps_without_labels(pic, wi):
+def test_steps_without_labels(pic, wi, rank):
     """Three cycles without particle labels (the kernel instantiation the benchmark runs, which
     has no label copy) against the oracle; the sorted orders are compared slot by slot."""
     wl = SMALL[wi]
-    _say(f"steps without labels {wl.name}")
+    _say(f"steps without labels {wl.name} rank={rank}")
     fields = picgen.random_fields(100 + wi, wl.grid, amp_e=0.05, amp_h=0.2)
     ctx, orc = setup_both(pic, wl, fields=fields, tile=(8, 2), track_ids=False)
+    ctx.set_rank_mode(rank)
     for _ in range(3):
         ctx.step(1)
         orc.step(1)
@@ -345,13 +352,18 @@ def test_tile_size_invariance(pic):
             assert rel_err(P[s]["ux"], P0[s]["ux"]) <= 1e-12
 
 
-def test_foil_full_size_one_cycle(pic):
+@pytest.mark.parametrize("rank", [0, 2])
+def test_foil_full_size_one_cycle(pic, rank):
     """The particle-dominated foil (1024 x 512, 2.6M particles) in the launch configuration the
-    benchmark times (automatic tiles, no labels), one cycle from the loaded state."""
+    benchmark times (automatic tiles and ranker, no labels; the automatic ranker walks tile rows
+    at 64 particles per cell), and with the one-thread-per-cell ranker: one cycle from the
+    loaded state."""
     wl = picgen.named("foil")
-    _say(f"foil full size {wl.n_particles} particles")
+    _say(f"foil full size {wl.n_particles} particles rank={rank}")
     ctx, orc = setup_both(pic, wl, track_ids=False)
+    ctx.set_rank_mode(rank)
     info0 = ctx.get_info()
+    assert info0["rank_mode"] == (1 if rank == 0 else rank)
     check_moments(ctx, orc)
     ctx.step(1)
     orc.step(1)
@@ -364,13 +376,17 @@ def test_foil_full_size_one_cycle(pic):
     ctx.close()
 
 
-def test_field_dominated_full_size_one_cycle(pic):
+@pytest.mark.parametrize("rank", [0, 1])
+def test_field_dominated_full_size_one_cycle(pic, rank):
     """The field-dominated run (2048 x 2048 cells, 0.1 n_c, 4 particles per cell and species:
     33.6M particles, with the laser entering at x = 0) at full size: the deposit of the loaded
-    state and one whole cycle (fields, moments, sorted particles) against the oracle."""
+    state and one whole cycle (fields, moments, sorted particles) against the oracle, with the
+    automatic ranker (one thread per cell at 4 particles per cell) and with the row walk."""
     wl = picgen.named("lowdensity")
-    _say(f"field-dominated full size {wl.n_particles} particles")
+    _say(f"field-dominated full size {wl.n_particles} particles rank={rank}")
     ctx, orc = setup_both(pic, wl, track_ids=False)
+    ctx.set_rank_mode(rank)
+    assert ctx.get_info()["rank_mode"] == (2 if rank == 0 else rank)
     check_moments(ctx, orc)
     ctx.step(1)
     orc.step(1)

@@ -336,6 +336,40 @@ def test_mur_boundary_absorbs_outgoing_pulse():
     assert np.max(np.abs(sim.E)) <= 0.03 * e_start
 
 
+def _vacuum_cycle_matrix(nx, nz, courant):
+    """The linear map of one vacuum cycle (E, H) -> (E', H') with Mur columns on x, column by
+    column through the oracle."""
+    g = _grid(nx=nx, nz=nz, dx=1.0, dz=1.0, dt=courant, bc_x=1, n_species=1)
+    nxn = nx + 1
+    nE, nH = 3 * nz * nxn, 3 * nz * nx
+    M = np.zeros((nE + nH, nE + nH))
+    for j in range(nE + nH):
+        v = np.zeros(nE + nH)
+        v[j] = 1.0
+        sim = OracleSim(g)
+        sim.load_fields(v[:nE].reshape(3, nz, nxn), v[nE:].reshape(3, nz, nx))
+        sim.step(1)
+        M[:, j] = np.concatenate([np.ravel(sim.E), np.ravel(sim.H)])
+    return M
+
+
+def test_mur_columns_growth_of_transverse_modes():
+    """What the first-order Mur reading does on the collocated grid, as eigenvalues of the
+    vacuum cycle.  Plane waves (one cell in z) are neutral: spectral radius 1.  A mode with
+    k_z dz = pi, which the 2 x 2 averaged curls of the interior do not see, is amplified at the
+    columns: it grows by about a factor 2 every nx cycles, so the growth per cycle falls with
+    the width, 1.049, 1.030, 1.017 at nx = 12, 24, 48 (Courant 0.4).  A long run on a narrow
+    box amplifies whatever noise reaches the columns; on the wide boxes of the workloads
+    (nx >= 1024) the factor over 1000 cycles stays of order a few."""
+    rho1 = np.max(np.abs(np.linalg.eigvals(_vacuum_cycle_matrix(12, 1, 0.4))))
+    assert abs(rho1 - 1.0) <= 1e-12
+    rhos = [np.max(np.abs(np.linalg.eigvals(_vacuum_cycle_matrix(nx, 2, 0.4)))) for nx in (12, 24, 48)]
+    assert 1.045 <= rhos[0] <= 1.052
+    assert rhos[0] > rhos[1] > rhos[2] > 1.0
+    for nx, r in zip((12, 24, 48), rhos):
+        assert 1.5 <= r ** nx <= 2.6
+
+
 def test_laser_source_enters_with_its_amplitude():
     """The x = 0 source (Step 4 with Mur on the scattered field) launches a wave whose peak E_y
     is the requested a0 to within grid dispersion and the low-order boundary."""
