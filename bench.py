@@ -433,14 +433,18 @@ def mover_options(binding, torch, steps):
     return res
 
 
-def batched(binding, torch, nruns, steps, warmup):
+def batched(binding, torch, nruns, steps, warmup, autotune=False):
     """The batched form in both precisions: `nruns` independent foil runs of uneven size (drawn
     like the serving stream: sides log-uniform in [32, 512], slab 5-15 % of x, density 10-200
     n_c, 8-64 particles per cell) stepped together by the persistent batch kernels with graph
     replay, first all in FP64, then all in mixed precision: aggregate particle-steps/s of each
-    (particles alive, averaged over the timed cycles) and the speedup of the mixed batch."""
+    (particles alive, averaged over the timed cycles) and the speedup of the mixed batch.  With
+    autotune, the tile shape is tuned on the whole batch (every member takes the candidate
+    shape at once, whole batch cycles are timed)."""
+    from paper_1308_2590_amd import autotune as at
     reqs = picgen.serving_stream(nruns, seed=11)
-    res = {"runs": nruns, "cycles": steps, "graph": True}
+    res = {"runs": nruns, "cycles": steps, "graph": True, "tiles": "tuned on the batch" if autotune
+           else "library default per run"}
     for name, prec in (("fp64", picgen.PREC_FP64), ("mixed", picgen.PREC_MIXED)):
         b = binding.Batch(0, prec)
         ctxs = []
@@ -452,6 +456,11 @@ def batched(binding, torch, nruns, steps, warmup):
             b.add(ctx)
             ctxs.append(ctx)
         b.set_graph(True)
+        if autotune:
+            tuned = at.tune_batch(b, ctxs)
+            res.setdefault("tuning", {})[name] = {
+                "best": list(tuned["best"]),
+                "ms_per_cycle": {f"{k[0]}x{k[1]}": v for k, v in tuned["ms_per_cycle"].items()}}
         b.step(warmup)
         b.sync()
         alive = lambda: sum(sum(c.get_info()["alive"]) for c in ctxs)
@@ -462,8 +471,12 @@ def batched(binding, torch, nruns, steps, warmup):
         b.sync()
         dt = time.perf_counter() - t0
         n1 = alive()
+        shapes = {}
+        for c in ctxs:
+            key = "x".join(str(v) for v in c.get_info()["tile"])
+            shapes[key] = shapes.get(key, 0) + 1
         res[name] = {"particles": n0, "ms_per_step": dt / steps * 1e3,
-                     "particle_steps_per_s": 0.5 * (n0 + n1) * steps / dt}
+                     "particle_steps_per_s": 0.5 * (n0 + n1) * steps / dt, "tile_shapes": shapes}
         b.close()
         for c in ctxs:
             c.close()
@@ -575,7 +588,7 @@ def main():
         print("[bench] mover options done", file=sys.stderr, flush=True)
     if args.batch_runs > 0:
         out["batched_fp64_vs_mixed"] = batched(binding, torch, args.batch_runs, args.batch_steps,
-                                               args.warmup)
+                                               args.warmup, bool(args.autotune))
         print("[bench] batched comparison done", file=sys.stderr, flush=True)
     if args.serve_runs > 0:
         out["serving"] = serving(args)

@@ -129,12 +129,14 @@ __device__ void deposit_one(const StepArgs &a, const SpeciesArgs &sp, int s, dou
 template <bool PUSH>
 __global__ __launch_bounds__(kBlock) void k_particles_alt(const StepArgs a, int mover) {
   const GridArgs &g = a.g;
-  // the next order's tile flags are set by the sort's scan; every tile may hold deposits
+  // the next order's tile flags are set by the sort's scan; every node may hold deposits
   if (blockIdx.y == 0) {
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < a.t.ntiles; t += gridDim.x * blockDim.x) {
-      if (PUSH) a.tile_active_next[t] = 0;
-      if (a.mtile) a.mtile[t] = 1;
-    }
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (PUSH)
+      for (int64_t t = t0; t < a.t.ntiles; t += stride) a.tile_active_next[t] = 0;
+    if (a.mflag)
+      for (int64_t f = t0; f < (a.g.nnodes + kFlagNodes - 1) / kFlagNodes; f += stride) a.mflag[f] = 1;
   }
   const int s = blockIdx.y;
   const SpeciesArgs &sp = a.sp[s];

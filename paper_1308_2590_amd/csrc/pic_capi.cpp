@@ -167,16 +167,21 @@ bool any_pw(const pic_ctx *c) {
 }
 
 // Tile size from the load.  One wavefront handles one row of a tile, each lane a contiguous
-// run of that row's particles, so a tile is 4 rows high and wide enough for a row to hold
-// about 1024 particles of a species (runs of ~16); a power of two in [4, 32], shrunk until
-// two blocks fit in the LDS of a CU (half the LDS a block may use).
-void choose_tiles(pic_ctx *c, int64_t total, int64_t occupied, int nspecies) {
+// run of that row's particles.  The rule follows what timing every candidate shape measured on
+// uniform and slab loads: tiles 32 cells wide (mixed precision: 8 wide above 16 particles per
+// occupied cell and species, since three wavefronts per SIMD want more, smaller blocks), and
+// as many rows (1 to 4) as bring a tile to about 4096 particles per species (mixed: 2048),
+// counting only the occupied cells of a row (a narrow slab fills a short part of each row).
+// Shrunk in x until two blocks fit in the LDS of a CU (half the LDS a block may use).
+// ppc: particles per occupied cell and species; width: occupied cells per occupied row.
+void choose_tiles(pic_ctx *c, double ppc, double width) {
   int tx = c->d.tile_x, tz = c->d.tile_z;
   if (tx <= 0 || tz <= 0) {
-    double ppc = occupied > 0 ? (double)total / (double)occupied / std::max(nspecies, 1) : 1.0;
-    tx = 4;
-    while (tx < 32 && (double)(2 * tx) * ppc <= 1024.0 * 1.4) tx *= 2;
-    tz = 4;
+    const bool mx = mixed(c);
+    tx = (mx && ppc > 16.0) ? 8 : 32;
+    const double per_row = std::max(1.0, std::min((double)tx, width) * ppc);
+    tz = (int)std::lround((mx ? 2048.0 : 4096.0) / per_row);
+    tz = std::min(4, std::max(1, tz));
     while (tx > 4 &&
            pic::particle_lds_bytes(c->g, pic::TileArgs{tx, tz, 0, 0, 0, 0}, mixed(c), any_pw(c)) >
                c->lds_max / 2)
@@ -262,7 +267,7 @@ pic::StepArgs step_args(pic_ctx *c, bool push) {
   a.tile_list = c->tlist[cur];
   a.tile_active_next = c->tact[nxt];
   a.tile_list_next = c->tlist[nxt];
-  a.mtile = c->mtile;
+  a.mflag = c->mflag;
   return a;
 }
 
@@ -278,18 +283,12 @@ pic_status alloc_tiles(pic_ctx *c) {
     c->tact[b] = nullptr;
     c->tlist[b] = nullptr;
   }
-  dfree(c, c->mtile, (size_t)std::max(c->tiles_alloc, 1));
-  c->mtile = nullptr;
   c->tiles_alloc = 0;
   pic_status st;
   for (int b = 0; b < 2; ++b) {
     if ((st = dalloc(c, &c->tact[b], (size_t)nt, "alloc tile flags")) != PIC_OK) return st;
     if ((st = dalloc(c, &c->tlist[b], (size_t)nt + 1, "alloc tile list")) != PIC_OK) return st;
   }
-  if ((st = dalloc(c, &c->mtile, (size_t)nt, "alloc deposit flags")) != PIC_OK) return st;
-  // Moments deposited under another tiling may sit anywhere: every node is read (and
-  // cleared) by the next field solve.
-  HIP_TRY(c, fill_wait(c, c->mtile, 1, (size_t)nt), "deposit flags");
   c->tiles_alloc = nt;
   return PIC_OK;
 }
@@ -348,8 +347,9 @@ pic_status particle_stage(pic_ctx *c, const pic::StepArgs &a) {
   return PIC_OK;
 }
 
-// Tile shape from the descriptor's tile_x / tile_z, or from the particles per occupied cell of
-// all loaded species when those are 0.  Waits for the stream (reads the cell starts).
+// Tile shape from the descriptor's tile_x / tile_z, or from the load when those are 0: the
+// particles per occupied cell and species, and the occupied cells per occupied row.  Waits
+// for the stream (reads the cell starts).
 pic_status retile(pic_ctx *c) {
   const int64_t nc = c->g.ncells;
   std::vector<uint8_t> occ((size_t)nc, 0);
@@ -366,11 +366,17 @@ pic_status retile(pic_ctx *c) {
       if (csh[cc + 1] > csh[cc]) occ[cc] = 1;
     total += csh[nc];
   }
-  int64_t occupied = 0;
-  for (uint8_t o : occ) occupied += o;
-  choose_tiles(c, total, occupied, nloaded);
-  c->rank_cells_auto = occupied > 0 && nloaded > 0 &&
-                       (double)total / ((double)occupied * nloaded) <= kRankCellsMaxPerCell;
+  int64_t occupied = 0, rows = 0;
+  for (int64_t k = 0; k < c->g.nz; ++k) {
+    int64_t in_row = 0;
+    for (int64_t i = 0; i < c->g.nx; ++i) in_row += occ[(size_t)(k * c->g.nx + i)];
+    occupied += in_row;
+    rows += in_row > 0 ? 1 : 0;
+  }
+  const double ppc = occupied > 0 ? (double)total / (double)occupied / std::max(nloaded, 1) : 1.0;
+  const double width = rows > 0 ? (double)occupied / (double)rows : (double)c->g.nx;
+  choose_tiles(c, ppc, width);
+  c->rank_cells_auto = occupied > 0 && ppc <= kRankCellsMaxPerCell;
   if (pic::particle_lds_bytes(c->g, c->tiles, mixed(c), any_pw(c)) > c->lds_max)
     return fail(c, PIC_ERR_ARG, "tile too large: its LDS accumulators exceed the LDS of a block");
   return PIC_OK;
@@ -423,10 +429,8 @@ FieldArgs cycle_field_args(pic_ctx *c, int p) {
   fa.H = c->H[p];
   fa.E_new = c->E[1 - p];
   fa.H_new = c->H[1 - p];
-  fa.mtile = c->mtile;
-  fa.tx = c->tiles.tx;
-  fa.tz = c->tiles.tz;
-  fa.ntx = c->tiles.ntx;
+  fa.mflag = c->mflag;
+  fa.ntiles_next = c->tiles.ntiles;
   fa.r2dx = 1.0 / (2.0 * c->g.dx);
   fa.r2dz = 1.0 / (2.0 * c->g.dz);
   return fa;
@@ -508,7 +512,7 @@ pic_status pic_init_grid(const pic_grid_desc *d, pic_ctx **out) {
                             d->laser_fwhm_t, d->laser_t_center};
   c->n_scan_blocks = (int32_t)((g.ncells + pic::kScanBlock - 1) / pic::kScanBlock);
   c->n_scan1_blocks = (int32_t)((g.ncells + pic::kScan1Block - 1) / pic::kScan1Block);
-  choose_tiles(c, 0, 0, 1);
+  choose_tiles(c, 1.0, (double)g.nx);
 
   pic_status st = PIC_OK;
   auto bail = [&](pic_status s2) {
@@ -526,6 +530,8 @@ pic_status pic_init_grid(const pic_grid_desc *d, pic_ctx **out) {
   }
   if ((st = dalloc(c, &c->M, (size_t)g.n_planes * nn, "alloc moments")) != PIC_OK) return bail(st);
   if ((st = dalloc(c, &c->flags, 1, "alloc flags")) != PIC_OK) return bail(st);
+  const size_t nflag = (nn + pic::kFlagNodes - 1) / pic::kFlagNodes;
+  if ((st = dalloc(c, &c->mflag, nflag, "alloc deposit flags")) != PIC_OK) return bail(st);
   // 8 doubles, then 8 floats
   if ((st = dalloc(c, &c->wconst64, 12, "alloc densities")) != PIC_OK) return bail(st);
   c->wconst32 = reinterpret_cast<float *>(c->wconst64 + PIC_MAX_SPECIES);
@@ -539,6 +545,8 @@ pic_status pic_init_grid(const pic_grid_desc *d, pic_ctx **out) {
   e = copy_wait(c, c->H[0], host.data(), 3 * nc * sizeof(double), hipMemcpyHostToDevice);
   if (e != hipSuccess) return bail(hip_fail(c, e, "upload H"));
   e = fill_wait(c, c->M, 0, (size_t)g.n_planes * nn * sizeof(double));
+  // the moments start at zero: no node holds a deposit
+  if (e == hipSuccess) e = fill_wait(c, c->mflag, 0, nflag);
   if (e != hipSuccess) return bail(hip_fail(c, e, "clear moments"));
   e = fill_wait(c, c->flags, 0, sizeof(uint32_t));
   if (e != hipSuccess) return bail(hip_fail(c, e, "clear flags"));
@@ -1021,7 +1029,7 @@ void pic_destroy(pic_ctx *c) {
     dfree(c, c->tact[b], (size_t)std::max(c->tiles_alloc, 1));
     dfree(c, c->tlist[b], ((size_t)c->tiles_alloc + 1) * sizeof(int32_t));
   }
-  dfree(c, c->mtile, (size_t)std::max(c->tiles_alloc, 1));
+  dfree(c, c->mflag, (size_t)(c->g.nnodes + pic::kFlagNodes - 1) / pic::kFlagNodes);
   c->mem.put_all();
   for (auto &p : c->prof_ev)
     for (int q = 0; q < 4; ++q) (void)hipEventDestroy(p.ev[q]);

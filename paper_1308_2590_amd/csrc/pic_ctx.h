@@ -77,7 +77,7 @@ struct pic_ctx {
   pic::DevAlloc mem;       // device memory of the context
   uint8_t *tact[2] = {};   // active-tile flags of the current / next order
   int32_t *tlist[2] = {};  // ordered active-tile lists, count at [ntiles]
-  uint8_t *mtile = nullptr;  // deposit flags of the tiles (nodes whose moments can be nonzero)
+  uint8_t *mflag = nullptr;  // deposit flags, one per kFlagNodes nodes (moments can be nonzero)
   int32_t tiles_alloc = 0, tiles_tx = 0, tiles_tz = 0;
   int64_t step = 0;
   size_t lds_max = 65536;  // LDS a block may use on the context's device

@@ -17,6 +17,7 @@ constexpr int kPermPad = 8;        // padding entries after each permutation arr
 constexpr int kSolveNodes = 2;     // nodes per thread in the E solve
 constexpr int kHCells = 2;         // cells per thread in the H update
 constexpr int kScanItems = 4;      // cells per thread in the count scan
+constexpr int kFlagNodes = 8;      // consecutive nodes per deposit flag
 constexpr int kScanBlock = kBlock * kScanItems;
 constexpr int kScan1Items = 4;      // cells per thread in the scan of a cycle's sort
 constexpr int kScan1Block = kBlock * kScan1Items;
@@ -93,7 +94,7 @@ struct StepArgs {
   const int32_t *tile_list;
   uint8_t *tile_active_next;
   int32_t *tile_list_next;
-  uint8_t *mtile;            // deposit flags set for every tile the fold reaches (may be NULL)
+  uint8_t *mflag;            // deposit flags (see FieldArgs): set for every node the fold adds to
   int32_t n_scan1_blocks;   // blocks of kScan1Block cells in a cycle's sort scan
 };
 
@@ -105,12 +106,13 @@ struct FieldArgs {
   const double *E;           // E^n
   const double *H;           // H^{n+1/2}
   double *E_new, *H_new;
-  // Deposit flags of the particle tiles (tx x tz cells, ntx per row): a node's moments are
-  // read only where the flag of the tile holding the node is set; the H update clears the
-  // flags for the next deposit.  NULL: every node is read and cleared.
-  uint8_t *mtile;
+  // Deposit flags, one per kFlagNodes consecutive nodes (node index n: flag n / kFlagNodes):
+  // a node's moments are read (and cleared) only where its flag is set, since the deposit sets
+  // the flag of every node it adds to; the H update clears the flags for the next deposit.
+  // NULL: every node is read and cleared.
+  uint8_t *mflag;
   uint8_t *tact_next;        // batched cycle: the next order's tile flags, cleared here (or NULL)
-  int32_t tx, tz, ntx;
+  int32_t ntiles_next;       // their count
   double r2dx, r2dz;         // 1 / (2 dx), 1 / (2 dz) of the centred differences
 };
 

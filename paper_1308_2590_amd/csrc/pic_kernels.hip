@@ -120,13 +120,10 @@ __device__ double incident_ey(const LaserArgs &L, double t, double x, double z) 
   return L.a0 * sin(L.omega * tau) * exp(-0.5 * sz * sz) * exp(-2.0 * 0.6931471805599453 * st * st);
 }
 
-// Whether the moment planes of node (i, k) can hold a deposit: the flag of the particle tile
-// holding the node (the extra x column of an absorbing axis goes with the last cell column).
-// Elsewhere the planes are zero.
-__device__ __forceinline__ bool node_deposited(const FieldArgs &a, int i, int k) {
-  if (!a.mtile) return true;
-  const int ci = min(i, a.g.nx - 1);
-  return a.mtile[(k / a.tz) * a.ntx + ci / a.tx] != 0;
+// Whether the moment planes of node n can hold a deposit: the flag of its run of kFlagNodes
+// nodes.  Elsewhere the planes are zero.
+__device__ __forceinline__ bool node_deposited(const FieldArgs &a, int64_t n) {
+  return !a.mflag || a.mflag[n / kFlagNodes] != 0;
 }
 
 // Zero every moment plane of node n once its values have been read, so the next deposit
@@ -165,7 +162,7 @@ __device__ __forceinline__ void node_load(const FieldArgs &a, int i, int k, Node
   in.n = n;
 #pragma unroll
   for (int r = 0; r < 3; ++r) in.e[r] = a.E[r * nn + n];
-  in.dep = node_deposited(a, i, k);
+  in.dep = node_deposited(a, n);
   if (in.dep) {
 #pragma unroll
     for (int r = 0; r < 9; ++r) in.S[r] = a.M[r * nn + n];
@@ -249,7 +246,7 @@ __device__ void mur_node(const FieldArgs &a, double tE, int i, int k, const doub
   }
   write_e(a, nb, en);
   // the boundary node takes deposits too; its planes are not used by the solve
-  if (node_deposited(a, i, k)) clear_node_moments(a, nb);
+  if (node_deposited(a, nb)) clear_node_moments(a, nb);
 }
 
 // Nodes n0, n0 + stride, ... of the E solve (kSolveNodes per thread, their inputs loaded
@@ -339,13 +336,12 @@ __device__ __forceinline__ void update_h_body(const FieldArgs &a, int64_t c0, in
     a.H_new[c] = hn[q][0];
     a.H_new[nc + c] = hn[q][1];
     a.H_new[2 * nc + c] = hn[q][2];
-    // The E solve has read the deposit flags: clear them for the next deposit (there are no
-    // more tiles than cells).
-    if (c < (int64_t)a.ntx * ((g.nz + a.tz - 1) / a.tz)) {
-      if (a.mtile) a.mtile[c] = 0;
-      // the next order's tile flags, set again by the sort's scan (batched cycle)
-      if (a.tact_next) a.tact_next[c] = 0;
-    }
+    // The E solve has read the deposit flags: clear them for the next deposit (there are
+    // fewer flags than cells: nodes <= 2 cells).
+    if (a.mflag && c < (nn + kFlagNodes - 1) / kFlagNodes) a.mflag[c] = 0;
+    // the next order's tile flags, set again by the sort's scan (batched cycle; there are no
+    // more tiles than cells)
+    if (a.tact_next && c < (int64_t)a.ntiles_next) a.tact_next[c] = 0;
   }
 }
 
@@ -1150,18 +1146,6 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
     }
   }
   __syncthreads();
-  // Flag every tile that holds a node the fold can reach (nodes i0-1 .. i0+tx+1 by
-  // k0-1 .. k0+tz+1): the field solve reads and clears the moment planes only there.  Six
-  // sample columns and rows cover every tile they cross, tx or tz of 1 included.
-  if (a.mtile && threadIdx.x < 36) {
-    const int sx = threadIdx.x % 6, sz = threadIdx.x / 6;
-    int gx = i0 + (sx < 3 ? sx - 1 : t.tx + sx - 4);
-    int gz = k0 + (sz < 3 ? sz - 1 : t.tz + sz - 4);
-    bool in = true;
-    if (g.bc_x == PIC_BC_PERIODIC) gx = wrap_t(gx, g.nx, nearx); else in = gx >= 0 && gx <= g.nx;
-    gz = wrap_t(gz, g.nz, nearz);
-    if (in) a.mtile[(gz / t.tz) * t.ntx + min(gx, g.nx - 1) / t.tx] = 1;
-  }
   // Fold the tile's accumulators into the global FP64 moment planes, one node per thread:
   // delta-j and the densities as they are; S-hat from the S-hat scalars of the (up to) four
   // cells around the node, each expanded with its cell's B (H^{n+3/2} after a push, H^{n+1/2}
@@ -1175,10 +1159,16 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
     if (g.bc_x == PIC_BC_PERIODIC) gx = wrap_t(gx, g.nx, nearx); else in = gx >= 0 && gx <= g.nx;
     const int gz = wrap_t(k0 - 1 + lzz, g.nz, nearz);
     const int64_t node = (int64_t)gz * g.nxn + gx;
+    // the field solve reads and clears the moment planes only under a set deposit flag: set
+    // the flag of every node this fold adds to
+    bool wrote = false;
     for (int pp = 0; pp < Lo.n_node; ++pp) {
       const double v = acc.node[pp * plane + idx];
       const int gp = pp < 3 ? 9 + pp : 12 + (pp - 3);
-      if (in && v != 0.0) unsafeAtomicAdd(&a.M[(int64_t)gp * nn + node], v);
+      if (in && v != 0.0) {
+        unsafeAtomicAdd(&a.M[(int64_t)gp * nn + node], v);
+        wrote = true;
+      }
     }
     double S[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     bool any = false;
@@ -1213,10 +1203,16 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
       S[8] += fma(A2, B2 * B2, A0);
       any = true;
     }
-    if (!any || !in) continue;
+    if (any && in) {
 #pragma unroll
-    for (int r = 0; r < 9; ++r)
-      if (S[r] != 0.0) unsafeAtomicAdd(&a.M[(int64_t)r * nn + node], S[r]);
+      for (int r = 0; r < 9; ++r) {
+        if (S[r] != 0.0) {
+          unsafeAtomicAdd(&a.M[(int64_t)r * nn + node], S[r]);
+          wrote = true;
+        }
+      }
+    }
+    if (wrote && a.mflag) a.mflag[node / kFlagNodes] = 1;
   }
 }
 
@@ -1843,11 +1839,23 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const StepArgs a) {
 
 // The run owning work item w: the largest r with pre[r] <= w (runs without items are skipped
 // because their prefix equals the next run's).
+// The run owning work item w: the last r with pre[r] <= w (pre is the exclusive prefix of the
+// runs' item counts, non-decreasing, pre[0] = 0; a run without items is skipped).  The 64
+// lanes of the wavefront each load one pivot, spaced evenly over the range left, and a ballot
+// keeps the interval of the last pivot <= w: one memory round trip per factor 64 of runs
+// (the item index is uniform across the wavefront, which must be whole).
 __device__ __forceinline__ int find_run(const int32_t *pre, int nruns, int w) {
-  int lo = 0, hi = nruns - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (pre[mid] <= w) lo = mid; else hi = mid - 1;
+  const int lane = threadIdx.x & 63;
+  int lo = 0, n = nruns;
+  while (n > 1) {
+    const int step = (n + 63) >> 6;
+    const int idx = lo + lane * step;
+    const bool le = idx < lo + n && pre[idx] <= w;
+    const uint64_t m = __ballot(le);
+    const int last = 63 - __clzll((long long)m);  // lane 0 holds pre[lo] <= w
+    const int nlo = lo + last * step;
+    n = min(step, lo + n - nlo);
+    lo = nlo;
   }
   return lo;
 }
