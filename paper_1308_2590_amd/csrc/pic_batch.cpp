@@ -167,6 +167,8 @@ pic_status rebuild(pic_batch *b) {
   l.grid_particles = std::max(1, per_p) * b->cus;
   l.grid_rank = std::max(1, per_r) * b->cus;
   l.grid_small = 8 * b->cus;
+  l.items_nodes = n > 0 ? pre[0 * (n + 1) + n] : 0;
+  l.items_cells = n > 0 ? pre[1 * (n + 1) + n] : 0;
   b->dirty = false;
   return PIC_OK;
 }

@@ -168,17 +168,18 @@ bool any_pw(const pic_ctx *c) {
 
 // Tile size from the load.  One wavefront handles one row of a tile, each lane a contiguous
 // run of that row's particles.  The rule follows what timing every candidate shape measured on
-// uniform and slab loads: tiles 32 cells wide (mixed precision: 8 wide above 16 particles per
-// occupied cell and species, since three wavefronts per SIMD want more, smaller blocks), and
-// as many rows (1 to 4) as bring a tile to about 4096 particles per species (mixed: 2048),
-// counting only the occupied cells of a row (a narrow slab fills a short part of each row).
+// uniform and slab loads: tiles 16 cells wide where the occupied part of a row is at most 16
+// cells (a narrow slab), otherwise 32, or 8 in mixed precision above 16 particles per occupied
+// cell and species (three wavefronts per SIMD want more, smaller blocks); and as many rows (1 to 4) as
+// bring a tile to about 4096 particles per species (mixed: 2048), counting only the occupied
+// cells of a row.
 // Shrunk in x until two blocks fit in the LDS of a CU (half the LDS a block may use).
 // ppc: particles per occupied cell and species; width: occupied cells per occupied row.
 void choose_tiles(pic_ctx *c, double ppc, double width) {
   int tx = c->d.tile_x, tz = c->d.tile_z;
   if (tx <= 0 || tz <= 0) {
     const bool mx = mixed(c);
-    tx = (mx && ppc > 16.0) ? 8 : 32;
+    tx = width <= 16.0 ? 16 : (mx && ppc > 16.0) ? 8 : 32;
     const double per_row = std::max(1.0, std::min((double)tx, width) * ppc);
     tz = (int)std::lround((mx ? 2048.0 : 4096.0) / per_row);
     tz = std::min(4, std::max(1, tz));

@@ -139,6 +139,8 @@ struct BatchLaunch {
   int32_t grid_small;        // persistent blocks of the element-wise and scan kernels
   int32_t grid_particles;    // persistent blocks of the particle kernel
   int32_t grid_rank;         // persistent blocks of the rank kernel
+  int32_t items_nodes;       // node blocks of all runs (one block each in the E solve)
+  int32_t items_cells;       // cell blocks of all runs (one block each in the H update)
   size_t lds_particles, lds_rank;
   bool mixed;
   bool ids;                  // some run copies particle ids (the kernel instantiation with ids)

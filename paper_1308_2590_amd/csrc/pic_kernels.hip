@@ -33,6 +33,7 @@
 // rounding (vector form of the response, Newton-refined reciprocals), so FP64 results agree
 // with the oracle to about 1e-15 relative per cycle.
 
+#include <algorithm>
 #include <type_traits>
 
 #include "pic_internal.h"
@@ -1875,22 +1876,23 @@ __device__ __forceinline__ const FieldArgs &run_field(const BatchArgs &b, int r)
   return *(const FieldArgs *)(t + 2 * r + p);
 }
 
-__global__ __launch_bounds__(kBlock) void kb_solve_e(const BatchArgs b) {
-  const int total = b.pre_nodes[b.nruns];
-  for (int w = blockIdx.x; w < total; w += gridDim.x) {
-    const int r = find_run(b.pre_nodes, b.nruns, w);
-    const FieldArgs &fa = run_field(b, r);
-    const double tE = (double)b.step_ctr[r] * fa.g.dt;
-    solve_e_body(fa, tE, (int64_t)(w - b.pre_nodes[r]) * (kSolveNodes * kBlock) + threadIdx.x, kBlock);
-  }
+// The field kernels' items (node and cell blocks of every run) do not change between
+// rebuilds of the batch, so these launch one block per item, with the items of each XCD a
+// contiguous band (as in a single run) instead of a persistent loop.
+__global__ __launch_bounds__(kBlock) void kb_solve_e(const BatchArgs b, int total) {
+  const int w = (int)xcd_band_block(total);
+  if (w < 0) return;
+  const int r = find_run(b.pre_nodes, b.nruns, w);
+  const FieldArgs &fa = run_field(b, r);
+  const double tE = (double)b.step_ctr[r] * fa.g.dt;
+  solve_e_body(fa, tE, (int64_t)(w - b.pre_nodes[r]) * (kSolveNodes * kBlock) + threadIdx.x, kBlock);
 }
 
-__global__ __launch_bounds__(kBlock) void kb_update_h(const BatchArgs b) {
-  const int total = b.pre_cells[b.nruns];
-  for (int w = blockIdx.x; w < total; w += gridDim.x) {
-    const int r = find_run(b.pre_cells, b.nruns, w);
-    update_h_body(run_field(b, r), (int64_t)(w - b.pre_cells[r]) * (kHCells * kBlock) + threadIdx.x, kBlock);
-  }
+__global__ __launch_bounds__(kBlock) void kb_update_h(const BatchArgs b, int total) {
+  const int w = (int)xcd_band_block(total);
+  if (w < 0) return;
+  const int r = find_run(b.pre_cells, b.nruns, w);
+  update_h_body(run_field(b, r), (int64_t)(w - b.pre_cells[r]) * (kHCells * kBlock) + threadIdx.x, kBlock);
 }
 
 // Work prefixes of the active tiles of every run's current order (one block).
@@ -2088,8 +2090,10 @@ static BatchParticlesKernel batch_particles_kernel(bool mixed, bool ids, bool pw
 
 hipError_t launch_batch_cycle(const BatchArgs &b, const BatchLaunch &l, hipStream_t s) {
   const dim3 blk(kBlock), small((unsigned)l.grid_small);
-  hipLaunchKernelGGL(kb_solve_e, small, blk, 0, s, b);
-  hipLaunchKernelGGL(kb_update_h, small, blk, 0, s, b);
+  hipLaunchKernelGGL(kb_solve_e, dim3(8u * (unsigned)std::max(1, (l.items_nodes + 7) / 8)), blk, 0,
+                     s, b, l.items_nodes);
+  hipLaunchKernelGGL(kb_update_h, dim3(8u * (unsigned)std::max(1, (l.items_cells + 7) / 8)), blk, 0,
+                     s, b, l.items_cells);
   hipLaunchKernelGGL(kb_prefix, dim3(1), dim3(1024), 0, s, b);
   const dim3 gp((unsigned)l.grid_particles);
   hipLaunchKernelGGL(batch_particles_kernel(l.mixed, l.ids, l.pw), gp, blk, l.lds_particles, s, b);
