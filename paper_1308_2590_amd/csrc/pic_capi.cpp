@@ -212,6 +212,7 @@ pic::StepArgs step_args(pic_ctx *c, bool push) {
   a.t = c->tiles;
   a.mixed = mixed(c) ? 1 : 0;
   a.rank_cells = rank_cells(c) ? 1 : 0;
+  a.chunk2 = c->chunk2 ? 1 : 0;
   a.n_scan_blocks = c->n_scan_blocks;
   a.n_scan1_blocks = c->n_scan1_blocks;
   a.nsp = c->S;
@@ -378,6 +379,13 @@ pic_status retile(pic_ctx *c) {
   const double width = rows > 0 ? (double)occupied / (double)rows : (double)c->g.nx;
   choose_tiles(c, ppc, width);
   c->rank_cells_auto = occupied > 0 && ppc <= kRankCellsMaxPerCell;
+  // particles per lane in a tile row (a row splits over the wavefronts when the tile has fewer
+  // rows than the block has wavefronts): chunks of 2 up to 2.5 of them
+  {
+    const int waves_per_row = c->tiles.tz >= 4 ? 1 : 4 / c->tiles.tz;
+    const double per_lane = std::min((double)c->tiles.tx, width) * ppc / (64.0 * waves_per_row);
+    c->chunk2 = occupied > 0 && per_lane <= 2.5;
+  }
   if (pic::particle_lds_bytes(c->g, c->tiles, mixed(c), any_pw(c)) > c->lds_max)
     return fail(c, PIC_ERR_ARG, "tile too large: its LDS accumulators exceed the LDS of a block");
   return PIC_OK;

@@ -84,6 +84,7 @@ struct pic_ctx {
   int32_t mover = 0;       // PIC_MOVER_* options; 0: the tile kernel's default mover
   int32_t rank_mode = PIC_RANK_AUTO;
   bool rank_cells_auto = false;  // the automatic choice, made with the tile shape
+  bool chunk2 = false;           // particle kernel chunk of 2 (about 2 particles per lane and row)
   int32_t n_scan_blocks = 0;
   int32_t n_scan1_blocks = 0;  // blocks of the scan of a cycle's sort
   std::string err;

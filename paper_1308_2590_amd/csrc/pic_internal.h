@@ -80,6 +80,7 @@ struct StepArgs {
   TileArgs t;
   int32_t mixed;             // 1: mixed-precision particle state and arithmetic
   int32_t rank_cells;        // 1: destinations ranked one thread per cell, 0: by tile rows
+  int32_t chunk2;            // 1: the particle kernel loads 2 particles per lane at a time, 0: 4
   int32_t n_scan_blocks;     // blocks of the count scan per species
   int32_t nsp;               // species slots
   SpeciesArgs sp[kMaxSpecies];

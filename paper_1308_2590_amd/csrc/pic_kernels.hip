@@ -678,8 +678,10 @@ struct Pstate<true> {
 // VGPRs (two waves per SIMD); the FP32 form fits three.  IDS adds the copy of particle ids
 // (tests only).  PW selects per-particle densities: each particle's moments are those of unit
 // density times its own density, which is read with the state and written with the pushed
-// state (a species with one density reads it from a one-element array with stride 0).
-template <bool PUSH, bool MIXED, bool IDS, bool PW>
+// state (a species with one density reads it from a one-element array with stride 0).  CH is
+// the chunk of particles a lane loads at once: 4, or 2 where a lane holds about two particles
+// per row (fewer registers and instructions when the chunk would be half empty).
+template <bool PUSH, bool MIXED, bool IDS, bool PW, int CH = 4>
 __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
   using T = typename std::conditional<MIXED, float, double>::type;
   const GridArgs &g = a.g;
@@ -851,22 +853,30 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
       // iteration lets it wait for the loads alone.  Loads are issued unconditionally (slots
       // past a lane's run read a location inside the state arrays, and their values go
       // unused): a load under a divergent branch also forces a full wait.
-      constexpr int kChunk = 4;
+      constexpr int kChunk = CH;
       Pstate<MIXED> cb[kChunk];
       int cp_[kChunk], np_[kChunk];
       T cw_[kChunk];
       // A chunk's permutation entries come in one 16-byte load per lane (the array is padded
       // so the load stays inside it); entries past the lane's run are clamped to a location
       // inside the state arrays and their particles go unused.
-      static_assert(kChunk == 4 && kPermPad >= 2 * kChunk, "one int4 of entries per chunk");
+      static_assert((kChunk == 4 || kChunk == 2) && kPermPad >= 2 * kChunk,
+                    "one int4 or int2 of entries per chunk");
       const uint32_t loc_max = (uint32_t)(sp.cap - 1);
       auto perm4 = [&](int first, int out[kChunk]) {
-        int4 v;
-        __builtin_memcpy(&v, perm + first, sizeof(v));
-        out[0] = (int)min((uint32_t)v.x, loc_max);
-        out[1] = (int)min((uint32_t)v.y, loc_max);
-        out[2] = (int)min((uint32_t)v.z, loc_max);
-        out[3] = (int)min((uint32_t)v.w, loc_max);
+        if constexpr (kChunk == 4) {
+          int4 v;
+          __builtin_memcpy(&v, perm + first, sizeof(v));
+          out[0] = (int)min((uint32_t)v.x, loc_max);
+          out[1] = (int)min((uint32_t)v.y, loc_max);
+          out[2] = (int)min((uint32_t)v.z, loc_max);
+          out[3] = (int)min((uint32_t)v.w, loc_max);
+        } else {
+          int2 v;
+          __builtin_memcpy(&v, perm + first, sizeof(v));
+          out[0] = (int)min((uint32_t)v.x, loc_max);
+          out[1] = (int)min((uint32_t)v.y, loc_max);
+        }
       };
       perm4(start, np_);
       // all lanes run the same number of iterations so the mover queue stays wave-uniform
@@ -1217,7 +1227,7 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
   }
 }
 
-template <bool PUSH, bool MIXED, bool IDS, bool PW>
+template <bool PUSH, bool MIXED, bool IDS, bool PW, int CH = 4>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2 + MIXED, 2 + MIXED)))
 void k_particles(const StepArgs a) {
   // clear the next order's tile flags (set by the scan of this cycle's sort); the grid has a
@@ -1225,7 +1235,7 @@ void k_particles(const StepArgs a) {
   if (threadIdx.x == 0 && (int)blockIdx.x < a.t.ntiles) a.tile_active_next[blockIdx.x] = 0;
   const int tile = block_tile(a.t, a.tile_list);
   if (tile < 0) return;
-  particles_body<PUSH, MIXED, IDS, PW>(a, tile);
+  particles_body<PUSH, MIXED, IDS, PW, CH>(a, tile);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -2023,6 +2033,14 @@ hipError_t launch_field_solve(const FieldArgs &a, hipStream_t s) {
 template <bool PUSH, bool MIXED>
 static void launch_particles_t(const StepArgs &a, bool ids, bool pw, dim3 grid, size_t lds,
                                hipStream_t s) {
+  // the pushing kernels without ids in the two-particle chunk form (few particles per lane)
+  if (PUSH && !ids && a.chunk2) {
+    if (pw)
+      hipLaunchKernelGGL((k_particles<PUSH, MIXED, false, true, 2>), grid, dim3(kBlock), lds, s, a);
+    else
+      hipLaunchKernelGGL((k_particles<PUSH, MIXED, false, false, 2>), grid, dim3(kBlock), lds, s, a);
+    return;
+  }
   if (PUSH && ids && pw)
     hipLaunchKernelGGL((k_particles<PUSH, MIXED, PUSH, true>), grid, dim3(kBlock), lds, s, a);
   else if (PUSH && ids)
