@@ -148,6 +148,7 @@ void free_species(pic_ctx *c, SpeciesState &s) {
   }
   dfree(c, s.locode, cap * sizeof(uint32_t)), s.locode = nullptr;
   dfree(c, s.cnt, (size_t)pic::kMoveCodes * nc * sizeof(int32_t)), s.cnt = nullptr;
+  dfree(c, s.cmask, nc * sizeof(uint16_t)), s.cmask = nullptr;
   dfree(c, s.arr, nc * sizeof(int32_t)), s.arr = nullptr;
   dfree(c, s.bsum, (size_t)c->n_scan_blocks * sizeof(int32_t)), s.bsum = nullptr;
   s.loaded = false;
@@ -213,6 +214,9 @@ pic::StepArgs step_args(pic_ctx *c, bool push) {
   a.mixed = mixed(c) ? 1 : 0;
   a.rank_cells = rank_cells(c) ? 1 : 0;
   a.chunk2 = c->chunk2 ? 1 : 0;
+  // the per-cell ranker reads code masks, which the tile kernel writes (not the per-particle
+  // kernel of the mover options, which accumulates full counts)
+  a.count_masks = (a.rank_cells && !c->mover) ? 1 : 0;
   a.n_scan_blocks = c->n_scan_blocks;
   a.n_scan1_blocks = c->n_scan1_blocks;
   a.nsp = c->S;
@@ -261,6 +265,7 @@ pic::StepArgs step_args(pic_ctx *c, bool push) {
     x.cs_new = st.cs[nxt];
     x.locode = st.locode;
     x.cnt = st.cnt;
+    x.cmask = st.cmask;
     x.arr = st.arr;
     x.bsum = st.bsum;
   }
@@ -637,6 +642,7 @@ pic_status pic_load_particles(pic_ctx *c, int32_t s, double q, double m, int64_t
   }
   if ((rs = dalloc(c, &st.locode, cap, "alloc codes")) != PIC_OK) return bail(rs);
   if ((rs = dalloc(c, &st.cnt, (size_t)pic::kMoveCodes * nc, "alloc counts")) != PIC_OK) return bail(rs);
+  if ((rs = dalloc(c, &st.cmask, (size_t)nc, "alloc code masks")) != PIC_OK) return bail(rs);
   if ((rs = dalloc(c, &st.arr, (size_t)nc, "alloc arrivals")) != PIC_OK) return bail(rs);
   if (fill_wait(c, st.arr, 0, (size_t)nc * sizeof(int32_t)) != hipSuccess)
     return bail(fail(c, PIC_ERR_DEVICE, "clear arrivals"));

@@ -47,6 +47,7 @@ struct SpeciesState {
   int32_t *cs[2] = {};     // cell start offsets [ncells + 1]
   uint32_t *locode = nullptr;
   int32_t *cnt = nullptr;  // [9][ncells]
+  uint16_t *cmask = nullptr;  // [ncells] move codes used per cell (with the per-cell ranker)
   int32_t *arr = nullptr;  // [ncells] arrivals per cell, zero between cycles
   int32_t *bsum = nullptr;
 };

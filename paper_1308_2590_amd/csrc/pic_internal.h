@@ -69,6 +69,9 @@ struct SpeciesArgs {
   int32_t *cs_new;           // cell start offsets of the next order [ncells + 1]
   uint32_t *locode;          // per sorted slot: (location written << 4) | move code
   int32_t *cnt;              // [9][ncells] particles leaving each cell per move code
+  // [ncells] bit d set when the cell sent particles with move code d; with count masks only
+  // the counts of set bits are written (the others keep values from earlier cycles)
+  uint16_t *cmask;
   int32_t *arr;              // [ncells] particles arriving in each cell; zero between cycles
   int32_t *bsum;             // block sums of the count scan
   int32_t cap;               // particle capacity of the state arrays
@@ -81,6 +84,7 @@ struct StepArgs {
   int32_t mixed;             // 1: mixed-precision particle state and arithmetic
   int32_t rank_cells;        // 1: destinations ranked one thread per cell, 0: by tile rows
   int32_t chunk2;            // 1: the particle kernel loads 2 particles per lane at a time, 0: 4
+  int32_t count_masks;       // 1: the particle kernel writes code masks and nonzero counts only
   int32_t n_scan_blocks;     // blocks of the count scan per species
   int32_t nsp;               // species slots
   SpeciesArgs sp[kMaxSpecies];

@@ -1136,12 +1136,19 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
         const int lkk = div_cw.q(e), li = e - lkk * cw;
         const int64_t cg = (int64_t)(k0 + lkk) * g.nx + (i0 + li);
         const int *cl = cntL + (lkk * t.tx + li) * 10;
+        uint32_t mask = 0;
 #pragma unroll
         for (int d = 0; d < kMoveCodes; ++d) {
           const int v = cl[d];
-          sp.cnt[(int64_t)d * nc + cg] = v;
-          if (v) atomicAdd(&arrL[(lkk + d / 3) * AW + (li + d % 3)], v);
+          // with code masks only the nonzero counts are written (most cells send all their
+          // particles with one code)
+          if (!a.count_masks || v) sp.cnt[(int64_t)d * nc + cg] = v;
+          if (v) {
+            mask |= 1u << d;
+            atomicAdd(&arrL[(lkk + d / 3) * AW + (li + d % 3)], v);
+          }
         }
+        if (a.count_masks) sp.cmask[cg] = (uint16_t)mask;
       }
       __syncthreads();
       for (int e = threadIdx.x; e < AW * AH; e += blockDim.x) {
@@ -1490,6 +1497,10 @@ __device__ __forceinline__ void rank_body(const StepArgs &a, int tile, int speci
 // after the wrap (one code per source and destination pair), so on grids one or two cells
 // wide a source listed under two codes has a zero count under the other.  No LDS and no
 // cross-lane work: for few particles per cell the row walk's per-tile staging costs more.
+// MASKS: the particle kernel wrote each cell's mask of used codes and only the nonzero counts
+// (most cells send every particle with one code), so a cell's own codes come from its mask
+// and a source's count is read only where the source's mask has the code.
+template <bool MASKS>
 __device__ __forceinline__ void rank_cells_body(const StepArgs &a, int tile, int species) {
   const GridArgs &g = a.g;
   const TileArgs &t = a.t;
@@ -1502,20 +1513,39 @@ __device__ __forceinline__ void rank_cells_body(const StepArgs &a, int tile, int
   const int total = sp.cs_new[g.ncells];
   const bool periodic_x = g.bc_x == PIC_BC_PERIODIC;
   const SmallDiv div_cw(cw);
+  // the count a source cell sent with code d2, valid only if the source holds particles now
+  // (with masks, read only where its mask has the code: the other counts are not written)
+  auto source_count = [&](int sc, int d2) -> int {
+    const int sb = sp.cs[sc], se = sp.cs[sc + 1];
+    if constexpr (MASKS) {
+      const uint32_t m = sp.cmask[sc];
+      return (se > sb && ((m >> d2) & 1u)) ? sp.cnt[(int64_t)d2 * g.ncells + sc] : 0;
+    } else {
+      const int v = sp.cnt[(int64_t)d2 * g.ncells + sc];
+      return se > sb ? v : 0;
+    }
+  };
   for (int e = threadIdx.x; e < ncell; e += blockDim.x) {
     const int lk = div_cw.q(e), li = e - lk * cw;
     const int ci = i0 + li, ck = k0 + lk;
     const int c = ck * g.nx + ci;
-    // Issued together: the cell's slot range and counts, its own next-order start, and the
-    // counts of the sources that precede it among the sources of its own cell as a destination
-    // (code 4, the particles that stay): in key order these are the row below and the left
-    // neighbour (codes 5 to 8); codes 0 to 3 come before it only through a wrap.
+    // Issued together: the cell's slot range and used codes, its own next-order start, and
+    // what the sources that precede it among the sources of its own cell as a destination
+    // (code 4, the particles that stay) sent it: in key order these are the row below and the
+    // left neighbour (codes 5 to 8); codes 0 to 3 come before it only through a wrap.
     const int cb = sp.cs[c], ce = sp.cs[c + 1];
     int cur[kMoveCodes];
+    if constexpr (MASKS) {
+      const uint32_t mc = sp.cmask[c];
 #pragma unroll
-    for (int d = 0; d < kMoveCodes; ++d) cur[d] = sp.cnt[(int64_t)d * g.ncells + c];
+      for (int d = 0; d < kMoveCodes; ++d) cur[d] = (int)((mc >> d) & 1u);
+    } else {
+#pragma unroll
+      for (int d = 0; d < kMoveCodes; ++d) cur[d] = sp.cnt[(int64_t)d * g.ncells + c];
+    }
     int stay = sp.cs_new[c];
     int pv[4], pb[4], pe[4];
+    uint32_t pmk[4];
     bool pm[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -1533,12 +1563,24 @@ __device__ __forceinline__ void rank_cells_body(const StepArgs &a, int tile, int
       pm[q] = in && sc < c;
       pb[q] = sp.cs[sc];
       pe[q] = sp.cs[sc + 1];
-      pv[q] = sp.cnt[(int64_t)d2 * g.ncells + sc];
+      if constexpr (MASKS) {
+        pmk[q] = sp.cmask[sc];
+        pv[q] = sc;
+      } else {
+        pmk[q] = ~0u;
+        pv[q] = sp.cnt[(int64_t)d2 * g.ncells + sc];
+      }
     }
     if (cb >= ce) continue;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (pm[q] && pe[q] > pb[q]) stay += pv[q];
+    for (int q = 0; q < 4; ++q) {
+      if (pm[q] && pe[q] > pb[q] && ((pmk[q] >> (5 + q)) & 1u)) {
+        if constexpr (MASKS)
+          stay += sp.cnt[(int64_t)(5 + q) * g.ncells + pv[q]];
+        else
+          stay += pv[q];
+      }
+    }
     if (ck == g.nz - 1 || (periodic_x && ci == g.nx - 1)) {
 #pragma unroll
       for (int d2 = 0; d2 < 4; ++d2) {
@@ -1552,11 +1594,7 @@ __device__ __forceinline__ void rank_cells_body(const StepArgs &a, int tile, int
         }
         if (sk >= g.nz) sk -= g.nz;
         const int sc = sk * g.nx + si;
-        if (in && sc < c) {
-          const int sb = sp.cs[sc], se = sp.cs[sc + 1];
-          const int v = sp.cnt[(int64_t)d2 * g.ncells + sc];
-          if (se > sb) stay += v;
-        }
+        if (in && sc < c) stay += source_count(sc, d2);
       }
     }
     // the other codes a cell uses (particles that change cell: few per cycle)
@@ -1589,11 +1627,7 @@ __device__ __forceinline__ void rank_cells_body(const StepArgs &a, int tile, int
         if (sk < 0) sk += g.nz;
         if (sk >= g.nz) sk -= g.nz;
         const int sc = sk * g.nx + si;
-        if (in && sc < c) {
-          const int sb = sp.cs[sc], se = sp.cs[sc + 1];
-          const int v = sp.cnt[(int64_t)d2 * g.ncells + sc];
-          if (se > sb) b += v;
-        }
+        if (in && sc < c) b += source_count(sc, d2);
       }
       cur[d] = b;
     }
@@ -1629,7 +1663,10 @@ __device__ __forceinline__ void rank_cells_body(const StepArgs &a, int tile, int
 __global__ __launch_bounds__(kBlock) void k_rank_cells(const StepArgs a) {
   const int tile = block_tile(a.t, a.tile_list);
   if (tile < 0) return;
-  rank_cells_body(a, tile, blockIdx.y);
+  if (a.count_masks)
+    rank_cells_body<true>(a, tile, blockIdx.y);
+  else
+    rank_cells_body<false>(a, tile, blockIdx.y);
 }
 
 __global__ __launch_bounds__(kBlock) void k_rank(const StepArgs a) {
@@ -1984,8 +2021,10 @@ __global__ __launch_bounds__(kBlock) void kb_rank(const BatchArgs b) {
     const StepArgs &sa = run_step(b, r);
     const int li = w - b.pre_rank[r];
     const int idx = li / sa.nsp;
-    if (sa.rank_cells)
-      rank_cells_body(sa, sa.tile_list[idx], li - idx * sa.nsp);
+    if (sa.rank_cells && sa.count_masks)
+      rank_cells_body<true>(sa, sa.tile_list[idx], li - idx * sa.nsp);
+    else if (sa.rank_cells)
+      rank_cells_body<false>(sa, sa.tile_list[idx], li - idx * sa.nsp);
     else
       rank_body(sa, sa.tile_list[idx], li - idx * sa.nsp);
     __syncthreads();
