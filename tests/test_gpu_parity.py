@@ -197,6 +197,29 @@ def test_steps_without_labels(pic, wi, rank):
     ctx.close()
 
 
+@pytest.mark.parametrize("wi", [0, 1, 4])
+def test_rank_mode_switches_between_cycles(pic, wi):
+    """The ranker changes every cycle (one thread per cell, tile rows, automatic) and the tiles
+    change once: the per-cell ranker's count masks leave counts of unused codes from earlier
+    cycles in the count planes, which neither ranker may read.  Six cycles against the oracle,
+    the order slot by slot."""
+    wl = SMALL[wi]
+    _say(f"rank mode switches {wl.name}")
+    fields = picgen.random_fields(300 + wi, wl.grid, amp_e=0.05, amp_h=0.2)
+    ctx, orc = setup_both(pic, wl, fields=fields)
+    for cyc, mode in enumerate([2, 1, 2, 0, 1, 2]):
+        ctx.set_rank_mode(mode)
+        if cyc == 3:
+            ctx.set_tiles(4, 2)
+        ctx.step(1)
+        orc.step(1)
+        check_fields(ctx, orc)
+        check_moments(ctx, orc)
+        check_particles(ctx, orc, wl)
+    assert ctx.get_info()["overflow_flags"] == 0
+    ctx.close()
+
+
 def test_laser_source_and_absorbing_boundary(pic):
     wl = picgen.random_small(42, nx=40, nz=12, ppc=2, bc_x=1, dx=0.3, dz=0.3, dt=0.2,
                              laser_a0=0.8)
