@@ -162,10 +162,15 @@ pic_status rebuild(pic_batch *b) {
   l.pw = pw;
   l.lds_particles = lds_p;
   l.lds_rank = lds_r;
-  int per_p = 1, per_r = 1;
-  BHIP(b, pic::batch_occupancy(l.mixed, l.ids, l.pw, lds_p, lds_r, &per_p, &per_r), "occupancy");
-  l.grid_particles = std::max(1, per_p) * b->cus;
-  l.grid_rank = std::max(1, per_r) * b->cus;
+  // one block per tile that any run could have active (the blocks past the cycle's active
+  // tiles return at once)
+  int64_t tiles_max = 0, rank_max = 0;
+  for (size_t r = 0; r < n; ++r) {
+    tiles_max += b->runs[r]->tiles.ntiles;
+    rank_max += (int64_t)b->runs[r]->tiles.ntiles * b->runs[r]->S;
+  }
+  l.grid_particles = (int32_t)std::max<int64_t>(1, tiles_max);
+  l.grid_rank = (int32_t)std::max<int64_t>(1, rank_max);
   l.grid_small = 8 * b->cus;
   l.items_nodes = n > 0 ? pre[0 * (n + 1) + n] : 0;
   l.items_cells = n > 0 ? pre[1 * (n + 1) + n] : 0;

@@ -121,8 +121,9 @@ struct FieldArgs {
   double r2dx, r2dz;         // 1 / (2 dx), 1 / (2 dz) of the centred differences
 };
 
-// Many independent runs stepped together, each kernel launched once for all of them
-// (persistent blocks looping over work items).  Per run, the step and field arguments for both
+// Many independent runs stepped together, each kernel launched once for all of them (a block
+// per work item for the field, particle and rank kernels, persistent blocks looping over the
+// items of the scans).  Per run, the step and field arguments for both
 // buffer parities live in device memory, and the run's current parity and cycle count are
 // device counters, so one captured cycle can be replayed for any mix of runs.
 struct BatchArgs {
@@ -141,9 +142,9 @@ struct BatchArgs {
 };
 
 struct BatchLaunch {
-  int32_t grid_small;        // persistent blocks of the element-wise and scan kernels
-  int32_t grid_particles;    // persistent blocks of the particle kernel
-  int32_t grid_rank;         // persistent blocks of the rank kernel
+  int32_t grid_small;        // persistent blocks of the scan kernels
+  int32_t grid_particles;    // blocks of the particle kernel: every tile of every run
+  int32_t grid_rank;         // blocks of the rank kernel: tiles x species of every run
   int32_t items_nodes;       // node blocks of all runs (one block each in the E solve)
   int32_t items_cells;       // cell blocks of all runs (one block each in the H update)
   size_t lds_particles, lds_rank;
@@ -183,9 +184,6 @@ hipError_t launch_energy_scratch(const StepArgs &a, const double *E, const doubl
 hipError_t launch_iota(int32_t *p, int64_t n, hipStream_t s);
 // One cycle of every run of a batch (field solve, particles, sort, counters).
 hipError_t launch_batch_cycle(const BatchArgs &b, const BatchLaunch &l, hipStream_t s);
-// Persistent blocks per CU of the batched particle and rank kernels at the given LDS sizes.
-hipError_t batch_occupancy(bool mixed, bool ids, bool pw, size_t lds_particles, size_t lds_rank,
-                           int *per_cu_particles, int *per_cu_rank);
 // Build the active-tile flags and list of the order described by sp[].cs (into
 // tile_active_next / tile_list_next).
 hipError_t launch_tile_list(const StepArgs &a, bool from_next_order, hipStream_t s);

@@ -1970,16 +1970,25 @@ __global__ __launch_bounds__(1024) void kb_prefix(const BatchArgs b) {
   }
 }
 
+// The particle and rank kernels' items (active tiles, and tiles x species) change every cycle;
+// they launch one block per item any run could have, and the blocks past the cycle's items
+// return at once, so the hardware hands the items, of very unequal cost, to the CUs as they
+// free up.  Block b takes item b: consecutive items (the tiles of one run) go to different
+// XCDs.  (Contiguous bands of items per XCD, as in a single run, were measured slower: runs
+// differ in cost, so the bands load the XCDs unequally.)
+__device__ __forceinline__ int batch_item(int total) {
+  const int w = (int)blockIdx.x;
+  return w < total ? w : -1;
+}
+
 template <bool MIXED, bool IDS, bool PW>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2 + MIXED, 2 + MIXED)))
 void kb_particles(const BatchArgs b) {
-  const int total = b.pre_tiles[b.nruns];
-  for (int w = blockIdx.x; w < total; w += gridDim.x) {
-    const int r = find_run(b.pre_tiles, b.nruns, w);
-    const StepArgs &sa = run_step(b, r);
-    particles_body<true, MIXED, IDS, PW>(sa, sa.tile_list[w - b.pre_tiles[r]]);
-    __syncthreads();
-  }
+  const int w = batch_item(b.pre_tiles[b.nruns]);
+  if (w < 0) return;
+  const int r = find_run(b.pre_tiles, b.nruns, w);
+  const StepArgs &sa = run_step(b, r);
+  particles_body<true, MIXED, IDS, PW>(sa, sa.tile_list[w - b.pre_tiles[r]]);
 }
 
 // The two-pass scan of every run's sort, as in a single run: pass 1 over (run, species, block
@@ -2015,20 +2024,18 @@ __global__ __launch_bounds__(kBlock) void kb_scan2(const BatchArgs b) {
 }
 
 __global__ __launch_bounds__(kBlock) void kb_rank(const BatchArgs b) {
-  const int total = b.pre_rank[b.nruns];
-  for (int w = blockIdx.x; w < total; w += gridDim.x) {
-    const int r = find_run(b.pre_rank, b.nruns, w);
-    const StepArgs &sa = run_step(b, r);
-    const int li = w - b.pre_rank[r];
-    const int idx = li / sa.nsp;
-    if (sa.rank_cells && sa.count_masks)
-      rank_cells_body<true>(sa, sa.tile_list[idx], li - idx * sa.nsp);
-    else if (sa.rank_cells)
-      rank_cells_body<false>(sa, sa.tile_list[idx], li - idx * sa.nsp);
-    else
-      rank_body(sa, sa.tile_list[idx], li - idx * sa.nsp);
-    __syncthreads();
-  }
+  const int w = batch_item(b.pre_rank[b.nruns]);
+  if (w < 0) return;
+  const int r = find_run(b.pre_rank, b.nruns, w);
+  const StepArgs &sa = run_step(b, r);
+  const int li = w - b.pre_rank[r];
+  const int idx = li / sa.nsp;
+  if (sa.rank_cells && sa.count_masks)
+    rank_cells_body<true>(sa, sa.tile_list[idx], li - idx * sa.nsp);
+  else if (sa.rank_cells)
+    rank_cells_body<false>(sa, sa.tile_list[idx], li - idx * sa.nsp);
+  else
+    rank_body(sa, sa.tile_list[idx], li - idx * sa.nsp);
 }
 
 // End of a cycle: flip every run's buffer parity and count the cycle.
@@ -2159,14 +2166,6 @@ hipError_t launch_batch_cycle(const BatchArgs &b, const BatchLaunch &l, hipStrea
   hipLaunchKernelGGL(kb_rank, dim3((unsigned)l.grid_rank), blk, l.lds_rank, s, b);
   hipLaunchKernelGGL(kb_end, dim3((unsigned)((b.nruns + kBlock - 1) / kBlock)), blk, 0, s, b);
   return hipGetLastError();
-}
-
-hipError_t batch_occupancy(bool mixed, bool ids, bool pw, size_t lds_particles, size_t lds_rank,
-                           int *per_cu_particles, int *per_cu_rank) {
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      per_cu_particles, batch_particles_kernel(mixed, ids, pw), kBlock, lds_particles);
-  if (e != hipSuccess) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_rank, kb_rank, kBlock, lds_rank);
 }
 
 hipError_t launch_iota(int32_t *p, int64_t n, hipStream_t s) {
