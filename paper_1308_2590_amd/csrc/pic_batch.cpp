@@ -26,7 +26,6 @@ struct pic_batch {
   int32_t *d_pre = nullptr;          // [6][cap + 1]
   pic::BatchArgs args{};
   pic::BatchLaunch launch{};
-  int cus = 0;
   bool dirty = true;
   bool use_graph = false;
   hipGraph_t graph = nullptr;
@@ -171,9 +170,9 @@ pic_status rebuild(pic_batch *b) {
   }
   l.grid_particles = (int32_t)std::max<int64_t>(1, tiles_max);
   l.grid_rank = (int32_t)std::max<int64_t>(1, rank_max);
-  l.grid_small = 8 * b->cus;
   l.items_nodes = n > 0 ? pre[0 * (n + 1) + n] : 0;
   l.items_cells = n > 0 ? pre[1 * (n + 1) + n] : 0;
+  l.items_scan = n > 0 ? pre[2 * (n + 1) + n] : 0;
   b->dirty = false;
   return PIC_OK;
 }
@@ -227,7 +226,7 @@ pic_status pic_batch_create(int32_t device, int32_t precision, pic_batch **out) 
   b->device = device;
   b->precision = precision;
   b->mem = pic::current_allocator(device);
-  hipDeviceProp_t prop;
+  hipDeviceProp_t prop;  // checks the device ordinal
   hipError_t e = hipGetDeviceProperties(&prop, device);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
@@ -235,7 +234,6 @@ pic_status pic_batch_create(int32_t device, int32_t precision, pic_batch **out) 
     delete b;
     return PIC_ERR_DEVICE;
   }
-  b->cus = prop.multiProcessorCount;
   *out = b;
   return PIC_OK;
 }

@@ -142,11 +142,11 @@ struct BatchArgs {
 };
 
 struct BatchLaunch {
-  int32_t grid_small;        // persistent blocks of the scan kernels
   int32_t grid_particles;    // blocks of the particle kernel: every tile of every run
   int32_t grid_rank;         // blocks of the rank kernel: tiles x species of every run
   int32_t items_nodes;       // node blocks of all runs (one block each in the E solve)
   int32_t items_cells;       // cell blocks of all runs (one block each in the H update)
+  int32_t items_scan;        // scan blocks x species of all runs (one block each in the scans)
   size_t lds_particles, lds_rank;
   bool mixed;
   bool ids;                  // some run copies particle ids (the kernel instantiation with ids)

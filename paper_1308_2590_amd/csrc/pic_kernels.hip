@@ -2153,7 +2153,7 @@ static BatchParticlesKernel batch_particles_kernel(bool mixed, bool ids, bool pw
 }
 
 hipError_t launch_batch_cycle(const BatchArgs &b, const BatchLaunch &l, hipStream_t s) {
-  const dim3 blk(kBlock), small((unsigned)l.grid_small);
+  const dim3 blk(kBlock);
   hipLaunchKernelGGL(kb_solve_e, dim3(8u * (unsigned)std::max(1, (l.items_nodes + 7) / 8)), blk, 0,
                      s, b, l.items_nodes);
   hipLaunchKernelGGL(kb_update_h, dim3(8u * (unsigned)std::max(1, (l.items_cells + 7) / 8)), blk, 0,
@@ -2161,8 +2161,10 @@ hipError_t launch_batch_cycle(const BatchArgs &b, const BatchLaunch &l, hipStrea
   hipLaunchKernelGGL(kb_prefix, dim3(1), dim3(1024), 0, s, b);
   const dim3 gp((unsigned)l.grid_particles);
   hipLaunchKernelGGL(batch_particles_kernel(l.mixed, l.ids, l.pw), gp, blk, l.lds_particles, s, b);
-  hipLaunchKernelGGL(kb_scan1, small, blk, 0, s, b);
-  hipLaunchKernelGGL(kb_scan2, small, blk, 0, s, b);
+  // the scans' items are fixed between rebuilds: a block per item (the kernels' loops then run
+  // once per block)
+  hipLaunchKernelGGL(kb_scan1, dim3((unsigned)std::max(1, l.items_scan)), blk, 0, s, b);
+  hipLaunchKernelGGL(kb_scan2, dim3((unsigned)std::max(1, l.items_scan + b.nruns)), blk, 0, s, b);
   hipLaunchKernelGGL(kb_rank, dim3((unsigned)l.grid_rank), blk, l.lds_rank, s, b);
   hipLaunchKernelGGL(kb_end, dim3((unsigned)((b.nruns + kBlock - 1) / kBlock)), blk, 0, s, b);
   return hipGetLastError();
