@@ -153,9 +153,9 @@ struct BatchLaunch {
   bool pw;                   // some run carries per-particle densities
 };
 
-// LDS of the particle kernel for a tile; pw: the instantiation with per-particle densities
-// (one more word per queued mover).
-size_t particle_lds_bytes(const GridArgs &g, const TileArgs &t, bool mixed, bool pw);
+// LDS of the particle kernel's block for a tile; pw: the instantiation with per-particle
+// densities (one more word per queued mover); queues: with the per-wavefront mover queues.
+size_t particle_lds_bytes(const GridArgs &g, const TileArgs &t, bool mixed, bool pw, bool queues = true);
 size_t rank_lds_bytes(const TileArgs &t);
 
 hipError_t launch_field_solve(const FieldArgs &a, hipStream_t s);

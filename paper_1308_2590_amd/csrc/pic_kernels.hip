@@ -580,6 +580,20 @@ __device__ __forceinline__ void drain_movers(const MoverQ<T> &q, int count, int 
   }
 }
 
+// One particle's compact moments added to the LDS accumulators of its cell (lower-left
+// accumulator node o, ring cell rc), corner by corner.
+template <typename T>
+__device__ __forceinline__ void deposit_one(const AccLds &acc, int o, int rc, T fx, T fz,
+                                            const Compact<T> &m, T w, int dplane) {
+#pragma unroll 1
+  for (int c = 0; c < 4; ++c) {
+    const int cx = c & 1, cz = c >> 1;
+    const T W = (cx ? fx : T(1) - fx) * (cz ? fz : T(1) - fz);
+    corner_add(acc, o + cx + cz * acc.LW, rc, c, W * m.a0, W * m.a1, W * m.a2, W * m.j0, W * m.j1,
+               W * m.j2, W * w, dplane);
+  }
+}
+
 // LDS layout of the particle kernel (byte offsets): the moment accumulators of the tile and its
 // halo (delta-j and density per node, S-hat scalars per corner of the tile's cells and their
 // one-cell ring), the fields the tile's particles read (E-bar on the tile's nodes, H^{n+1/2} on
@@ -611,7 +625,8 @@ struct TileLds {
     ho = eb + 3 * (size_t)EPL * tsize;
     hn = ho + 3 * (size_t)HPL * tsize;
     mq = (hn + 3 * (size_t)NPL * tsize + 7) & ~(size_t)7;
-    cnt = mq + (size_t)(kBlock / 64) * kMqCap * ((size_t)qwords * tsize + 2 * sizeof(int));
+    // qwords 0: no mover queues (the kernel form that deposits every particle at once)
+    cnt = mq + (qwords ? (size_t)(kBlock / 64) * kMqCap * ((size_t)qwords * tsize + 2 * sizeof(int)) : 0);
     arr = cnt + (size_t)tx * tz * 10 * sizeof(int);
     rows = arr + (size_t)(tx + 2) * (tz + 2) * sizeof(int);
     bytes = rows + (size_t)(n_node - 3) * tz * 2 * sizeof(int);
@@ -695,7 +710,7 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
   extern __shared__ double lds[];
   char *ldsb = reinterpret_cast<char *>(lds);
   constexpr int kQw = mq_words(PW);
-  const TileLds Lo(g.n_planes, t.tx, t.tz, (int)sizeof(T), kQw);
+  const TileLds Lo(g.n_planes, t.tx, t.tz, (int)sizeof(T), (PUSH && CH == 2) ? 0 : kQw);
   const AccLds acc{reinterpret_cast<double *>(ldsb + Lo.acc),
                    reinterpret_cast<double *>(ldsb + Lo.accc), Lo.plane, Lo.NPL, Lo.LW, Lo.NW};
   T *Eb = reinterpret_cast<T *>(ldsb + Lo.eb);
@@ -854,6 +869,10 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
       // past a lane's run read a location inside the state arrays, and their values go
       // unused): a load under a divergent branch also forces a full wait.
       constexpr int kChunk = CH;
+      // two particles per chunk: the form for about two particles per lane and row, where a
+      // lane's register sums would hold one or two particles; it deposits each particle into
+      // LDS directly (no register sums, row-end reduction or mover queue: fewer registers)
+      constexpr bool kDirect = PUSH && CH == 2;
       Pstate<MIXED> cb[kChunk];
       int cp_[kChunk], np_[kChunk];
       T cw_[kChunk];
@@ -1044,8 +1063,10 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
                 fz2 = zn - (double)k2;
               }
               if (newcell) {
-                if (ca.cell >= 0) ca.flush(acc, lz, dplane);
-                ca.clear();
+                if constexpr (!kDirect) {
+                  if (ca.cell >= 0) ca.flush(acc, lz, dplane);
+                  ca.clear();
+                }
                 ca.cell = li;
               }
               if constexpr (MIXED) {
@@ -1080,8 +1101,12 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
                 if (IDS && sp.dst_id) sp.dst_id[jb + it * 64 + lane] = sp.src_id[p];
                 atomicAdd(&cntL[hc * 10 + code], 1);
               }
-              // stayers add to the lane's accumulator, movers go through the queue
-              if (alive && code == 4u) {
+              // stayers add to the lane's accumulator, movers go through the queue (with few
+              // particles per lane every particle goes to the LDS accumulators at once)
+              if (kDirect) {
+                if (alive)
+                  deposit_one(acc, (lz + dk) * LW + (li + 1 + di), hn, fx2, fz2, m, wp, dplane);
+              } else if (alive && code == 4u) {
                 ca.add(fx2, fz2, m, wp);
               } else if (alive) {
                 mover = true;
@@ -1116,7 +1141,7 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
           }
         }
       }
-      ca.flush_row_end(acc, lz, dplane, lane);
+      if constexpr (!kDirect) ca.flush_row_end(acc, lz, dplane, lane);
       if (PUSH && nq > 0) {
         wave_sync();
         drain_movers<T, PW>(mq, nq, lane, acc, dplane, K.w);
@@ -1234,8 +1259,11 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
   }
 }
 
+// Waves per SIMD: the register sums of the chunks of 4 hold two FP64 waves (three mixed); the
+// chunk-of-2 form, without them, holds one more.
 template <bool PUSH, bool MIXED, bool IDS, bool PW, int CH = 4>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2 + MIXED, 2 + MIXED)))
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(2 + MIXED + (CH == 2), 2 + MIXED + (CH == 2))))
 void k_particles(const StepArgs a) {
   // clear the next order's tile flags (set by the scan of this cycle's sort); the grid has a
   // block for every tile index
@@ -1845,7 +1873,10 @@ __device__ __forceinline__ void scan2_body(const StepArgs &a, int bx, int s) {
   const int nb = a.n_scan1_blocks;
   const SpeciesArgs &sp = a.sp[s];
   if (!sp.active) return;
+  // the totals of the blocks before this one (up to 16 per thread on a 2048 x 2048 grid):
+  // unrolled so that a thread's loads are issued together
   int part = 0;
+#pragma unroll 8
   for (int b = threadIdx.x; b < bx; b += blockDim.x) part += sp.bsum[b];
   int prefix;
   (void)block_excl_scan(part, sh, &prefix);
@@ -1879,10 +1910,9 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const StepArgs a) {
 }
 
 // ------------------------------------------------------------------------------------------
-// Batched cycle: every kernel launched once for all runs of a batch.  Persistent blocks loop
-// over the work items of all runs (a run's items are numbered after the previous runs'); the
-// run of an item is found by binary search in the exclusive prefix of item counts.  Between
-// items a block synchronises, so LDS is reused safely.
+// Batched cycle: every kernel launched once for all runs of a batch, one block per work item
+// of all runs (a run's items are numbered after the previous runs'); the run of an item is
+// found in the exclusive prefix of item counts.
 // ------------------------------------------------------------------------------------------
 
 // The run owning work item w: the largest r with pre[r] <= w (runs without items are skipped
@@ -2054,9 +2084,9 @@ __global__ void k_iota(int32_t *p, int64_t n) {
 
 }  // namespace
 
-size_t particle_lds_bytes(const GridArgs &g, const TileArgs &t, bool mixed, bool pw) {
+size_t particle_lds_bytes(const GridArgs &g, const TileArgs &t, bool mixed, bool pw, bool queues) {
   return TileLds(g.n_planes, t.tx, t.tz, mixed ? (int)sizeof(float) : (int)sizeof(double),
-                 mq_words(pw)).bytes;
+                 queues ? mq_words(pw) : 0).bytes;
 }
 
 size_t rank_lds_bytes(const TileArgs &t) {
@@ -2080,12 +2110,14 @@ template <bool PUSH, bool MIXED>
 static void launch_particles_t(const StepArgs &a, bool ids, bool pw, dim3 grid, size_t lds,
                                hipStream_t s) {
   // the pushing kernels without ids in the two-particle chunk form (few particles per lane)
-  if (PUSH && !ids && a.chunk2) {
-    if (pw)
-      hipLaunchKernelGGL((k_particles<PUSH, MIXED, false, true, 2>), grid, dim3(kBlock), lds, s, a);
-    else
-      hipLaunchKernelGGL((k_particles<PUSH, MIXED, false, false, 2>), grid, dim3(kBlock), lds, s, a);
-    return;
+  if constexpr (PUSH) {
+    if (!ids && a.chunk2) {
+      if (pw)
+        hipLaunchKernelGGL((k_particles<PUSH, MIXED, false, true, 2>), grid, dim3(kBlock), lds, s, a);
+      else
+        hipLaunchKernelGGL((k_particles<PUSH, MIXED, false, false, 2>), grid, dim3(kBlock), lds, s, a);
+      return;
+    }
   }
   if (PUSH && ids && pw)
     hipLaunchKernelGGL((k_particles<PUSH, MIXED, PUSH, true>), grid, dim3(kBlock), lds, s, a);
@@ -2103,7 +2135,8 @@ hipError_t launch_particles(const StepArgs &a, bool push, hipStream_t s) {
     ids = ids || a.sp[q].dst_id != nullptr;
     pw = pw || (a.sp[q].active && a.sp[q].w_stride != 0);
   }
-  const size_t lds = particle_lds_bytes(a.g, a.t, a.mixed != 0, pw);
+  // the chunk-of-2 pushing form has no mover queues
+  const size_t lds = particle_lds_bytes(a.g, a.t, a.mixed != 0, pw, !(push && a.chunk2 && !ids));
   const dim3 grid(8u * (unsigned)a.t.per_xcd);
   if (a.mixed) {
     if (push) launch_particles_t<true, true>(a, ids, pw, grid, lds, s);
