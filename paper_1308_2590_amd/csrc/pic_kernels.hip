@@ -581,12 +581,16 @@ __device__ __forceinline__ void drain_movers(const MoverQ<T> &q, int count, int 
 }
 
 // One particle's compact moments added to the LDS accumulators of its cell (lower-left
-// accumulator node o, ring cell rc), corner by corner.
+// accumulator node o, ring cell rc), corner by corner.  Lanes of odd index take the corners in
+// the order (i,k+1), (i+1,k+1), (i,k), (i+1,k): neighbouring lanes often hold particles of one
+// cell, and same-address atomics of one instruction are serialised (different rows cost less).
 template <typename T>
 __device__ __forceinline__ void deposit_one(const AccLds &acc, int o, int rc, T fx, T fz,
                                             const Compact<T> &m, T w, int dplane) {
+  const int rot = (threadIdx.x & 1) << 1;
 #pragma unroll 1
-  for (int c = 0; c < 4; ++c) {
+  for (int c0 = 0; c0 < 4; ++c0) {
+    const int c = (c0 + rot) & 3;
     const int cx = c & 1, cz = c >> 1;
     const T W = (cx ? fx : T(1) - fx) * (cz ? fz : T(1) - fz);
     corner_add(acc, o + cx + cz * acc.LW, rc, c, W * m.a0, W * m.a1, W * m.a2, W * m.j0, W * m.j1,
@@ -597,9 +601,9 @@ __device__ __forceinline__ void deposit_one(const AccLds &acc, int o, int rc, T 
 // LDS layout of the particle kernel (byte offsets): the moment accumulators of the tile and its
 // halo (delta-j and density per node, S-hat scalars per corner of the tile's cells and their
 // one-cell ring), the fields the tile's particles read (E-bar on the tile's nodes, H^{n+1/2} on
-// its cells, H^{n+3/2} on its cells plus the ring), the per-wave mover queues, the int move
-// counters, the arrival counts of the tile's cells and their ring, and the first and end slot
-// of every tile row of every species slot.  Accumulators are FP64; fields and queues use the
+// its cells, H^{n+3/2} on its cells plus the ring), the per-wave mover queues, per species the
+// int move counters of the tile's cells and the arrival counts of the tile's cells and their
+// ring, and the first and end slot of every tile row of every species slot.  Accumulators are FP64; fields and queues use the
 // kernel's arithmetic type.
 struct TileLds {
   int LW, LH, plane;          // accumulator node grid (tx + 3) x (tz + 3)
@@ -627,8 +631,8 @@ struct TileLds {
     mq = (hn + 3 * (size_t)NPL * tsize + 7) & ~(size_t)7;
     // qwords 0: no mover queues (the kernel form that deposits every particle at once)
     cnt = mq + (qwords ? (size_t)(kBlock / 64) * kMqCap * ((size_t)qwords * tsize + 2 * sizeof(int)) : 0);
-    arr = cnt + (size_t)tx * tz * 10 * sizeof(int);
-    rows = arr + (size_t)(tx + 2) * (tz + 2) * sizeof(int);
+    arr = cnt + (size_t)(n_node - 3) * tx * tz * kMoveCodes * sizeof(int);
+    rows = arr + (size_t)(n_node - 3) * (tx + 2) * (tz + 2) * sizeof(int);
     bytes = rows + (size_t)(n_node - 3) * tz * 2 * sizeof(int);
   }
 };
@@ -689,8 +693,9 @@ struct Pstate<true> {
 // particle at iteration `it` of lane `l` is written to location row_start + 64 it + l, which
 // makes the stores (and next cycle's loads through the permutation) coalesced.
 // MIXED selects the mixed-precision form: FP32 state, gather, push and per-lane partial sums,
-// added into FP64 LDS accumulators and the FP64 moment planes.  The FP64 form needs about 250
-// VGPRs (two waves per SIMD); the FP32 form fits three.  IDS adds the copy of particle ids
+// added into FP64 LDS accumulators and the FP64 moment planes.  With chunks of 4 the FP64 form
+// needs about 230 VGPRs (two waves per SIMD) and the FP32 form about 150 (three); the
+// chunk-of-2 form needs about 130 and 105.  IDS adds the copy of particle ids
 // (tests only).  PW selects per-particle densities: each particle's moments are those of unit
 // density times its own density, which is read with the state and written with the pushed
 // state (a species with one density reads it from a one-element array with stride 0).  CH is
@@ -722,6 +727,12 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
   const int n_acc = Lo.n_node * plane + 12 * Lo.NPL;  // node planes, then cell-corner planes
 
   for (int e = threadIdx.x; e < n_acc; e += blockDim.x) acc.node[e] = 0.0;
+  const int AW = t.tx + 2, AH = t.tz + 2;  // arrival counts: the tile's cells and their ring
+  if (PUSH) {
+    const int nsl = Lo.n_node - 3;
+    for (int e = threadIdx.x; e < nsl * ntc * kMoveCodes; e += blockDim.x) cntL[e] = 0;
+    for (int e = threadIdx.x; e < nsl * AW * AH; e += blockDim.x) arrL[e] = 0;
+  }
   // a tile and its two-cell ring fit in the grid along an axis: wraps need one compare there
   const bool nearx = g.nx >= t.tx + 3, nearz = g.nz >= t.tz + 3;
   // Stage the fields of the tile and the slot range of every tile row of every species in one
@@ -816,10 +827,7 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
   for (int s = 0; s < a.nsp; ++s) {
     const SpeciesArgs &sp = a.sp[s];
     if (!sp.active) continue;
-    if (PUSH) {
-      for (int e = threadIdx.x; e < ntc * 10; e += blockDim.x) cntL[e] = 0;
-      __syncthreads();
-    }
+    int *const cntS = cntL + s * ntc * kMoveCodes;  // the species' move counters
     const SpConst<T> K{(T)sp.beta, (T)(PW ? sp.cS1 : sp.cS), (T)(PW ? sp.kJ1 : sp.kJ), (T)sp.w};
     const typename Pstate<MIXED>::Src src(sp);
     // per-particle densities: index p * wstride (stride 0 reads a species' single density)
@@ -1099,7 +1107,7 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
                 // particle ids (tests only): a separate instantiation, so that its load, which
                 // is waited for at once, does not enter the wait counts of the kernel without ids
                 if (IDS && sp.dst_id) sp.dst_id[jb + it * 64 + lane] = sp.src_id[p];
-                atomicAdd(&cntL[hc * 10 + code], 1);
+                if (code != kAbsorbed) atomicAdd(&cntS[hc * kMoveCodes + code], 1);
               }
               // stayers add to the lane's accumulator, movers go through the queue (with few
               // particles per lane every particle goes to the LDS accumulators at once)
@@ -1148,19 +1156,24 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
         wave_sync();
       }
     }
-    if (PUSH) {
-      // Move counts of the tile's cells (for the ranking), and the particles they send to
-      // each cell of the tile and its ring, summed in LDS and added to the per-cell arrival
-      // counts (the sort's scan reads those instead of gathering nine counts per cell).
-      const int AW = t.tx + 2, AH = t.tz + 2;
-      for (int e = threadIdx.x; e < AW * AH; e += blockDim.x) arrL[e] = 0;
-      __syncthreads();
-      const int cw = i1 - i0, chh = k1 - k0;
+  }
+  __syncthreads();
+  // Move counts of the tile's cells (for the ranking), and the particles they send to each cell
+  // of the tile and its ring, summed in LDS (added to the per-cell arrival counts after the
+  // fold: the sort's scan reads those instead of gathering nine counts per cell).  The counts
+  // of every species are kept until here, so the species need no barriers between them.
+  const int cw = i1 - i0, chh = k1 - k0;
+  for (int s = 0; s < a.nsp; ++s) {
+    const SpeciesArgs &sp = a.sp[s];
+    if (!PUSH || !sp.active) continue;
+    const int *cntS = cntL + s * ntc * kMoveCodes;
+    int *arrS = arrL + s * AW * AH;
+    {
       const SmallDiv div_cw(cw);
       for (int e = threadIdx.x; e < chh * cw; e += blockDim.x) {
         const int lkk = div_cw.q(e), li = e - lkk * cw;
         const int64_t cg = (int64_t)(k0 + lkk) * g.nx + (i0 + li);
-        const int *cl = cntL + (lkk * t.tx + li) * 10;
+        const int *cl = cntS + (lkk * t.tx + li) * kMoveCodes;
         uint32_t mask = 0;
 #pragma unroll
         for (int d = 0; d < kMoveCodes; ++d) {
@@ -1170,25 +1183,13 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
           if (!a.count_masks || v) sp.cnt[(int64_t)d * nc + cg] = v;
           if (v) {
             mask |= 1u << d;
-            atomicAdd(&arrL[(lkk + d / 3) * AW + (li + d % 3)], v);
+            atomicAdd(&arrS[(lkk + d / 3) * AW + (li + d % 3)], v);
           }
         }
         if (a.count_masks) sp.cmask[cg] = (uint16_t)mask;
       }
-      __syncthreads();
-      for (int e = threadIdx.x; e < AW * AH; e += blockDim.x) {
-        const int v = arrL[e];
-        if (v == 0) continue;
-        const int az = SmallDiv(AW).q(e), ax = e - az * AW;
-        int gi = i0 - 1 + ax;
-        const int gk = wrap1(k0 - 1 + az, g.nz);
-        if (g.bc_x == PIC_BC_PERIODIC) gi = wrap1(gi, g.nx);
-        atomicAdd(&sp.arr[(int64_t)gk * g.nx + gi], v);
-      }
-      __syncthreads();
     }
   }
-  __syncthreads();
   // Fold the tile's accumulators into the global FP64 moment planes, one node per thread:
   // delta-j and the densities as they are; S-hat from the S-hat scalars of the (up to) four
   // cells around the node, each expanded with its cell's B (H^{n+3/2} after a push, H^{n+1/2}
@@ -1256,6 +1257,23 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
       }
     }
     if (wrote && a.mflag) a.mflag[node / kFlagNodes] = 1;
+  }
+  if (PUSH) {
+    __syncthreads();
+    for (int s = 0; s < a.nsp; ++s) {
+      const SpeciesArgs &sp = a.sp[s];
+      if (!sp.active) continue;
+      const int *arrS = arrL + s * AW * AH;
+      for (int e = threadIdx.x; e < AW * AH; e += blockDim.x) {
+        const int v = arrS[e];
+        if (v == 0) continue;
+        const int az = SmallDiv(AW).q(e), ax = e - az * AW;
+        int gi = i0 - 1 + ax;
+        const int gk = wrap1(k0 - 1 + az, g.nz);
+        if (g.bc_x == PIC_BC_PERIODIC) gi = wrap1(gi, g.nx);
+        atomicAdd(&sp.arr[(int64_t)gk * g.nx + gi], v);
+      }
+    }
   }
 }
 
