@@ -178,6 +178,36 @@ def test_steps_from_identical_state(pic, wi, tile, rank):
 
 
 @pytest.mark.parametrize("rank", [1, 2])
+@pytest.mark.parametrize("ppc", [2, 12])
+@pytest.mark.parametrize("nsp", [4, 8])
+def test_many_species(pic, nsp, ppc, rank):
+    """Four and eight species (the move counts of every species are kept in LDS until the end
+    of a tile): two particles per cell take the chunk-of-2 kernel, twelve the chunk-of-4 one;
+    with eight species the default tile is narrowed until its LDS fits."""
+    masses = tuple(1.0 + 3.0 * s for s in range(nsp))
+    charges = tuple(-1.0 if s % 2 == 0 else 1.0 + 0.5 * s for s in range(nsp))
+    temps = tuple(0.5 + 0.7 * s for s in range(nsp))
+    dens = tuple(0.3 + 0.1 * s for s in range(nsp))
+    wl = picgen.random_small(500 + nsp + ppc, nx=20, nz=9, ppc=ppc, bc_x=nsp % 2, dx=0.5, dz=0.4,
+                             dt=0.3, masses=masses, charges=charges, temps=temps, density=dens)
+    _say(f"many species {wl.name} nsp={nsp} ppc={ppc} rank={rank}")
+    fields = picgen.random_fields(300 + nsp, wl.grid, amp_e=0.05, amp_h=0.2)
+    ctx, orc = setup_both(pic, wl, fields=fields)
+    ctx.set_rank_mode(rank)
+    check_moments(ctx, orc)
+    for _ in range(3):
+        ctx.step(1)
+        orc.step(1)
+        check_fields(ctx, orc)
+        check_moments(ctx, orc)
+        check_particles(ctx, orc, wl)
+    info = ctx.get_info()
+    assert info["overflow_flags"] == 0
+    assert info["alive"] == [orc.species[s].n for s in range(nsp)]
+    ctx.close()
+
+
+@pytest.mark.parametrize("rank", [1, 2])
 @pytest.mark.parametrize("wi", [0, 1, 3])
 def test_steps_without_labels(pic, wi, rank):
     """Three cycles without particle labels (the kernel instantiation the benchmark runs, which
