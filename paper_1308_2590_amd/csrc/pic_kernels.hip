@@ -491,7 +491,7 @@ struct CellAcc {
     }
   }
   // The accumulated cell is (cell, lz - 1) of the tile: ring cell (cell + 1, lz), whose
-  // lower-left node is (cell + 1, lz) locally.
+  // lower-left node is (cell + 1, lz) locally (the layout with the ring).
   __device__ __forceinline__ void flush(const AccLds &acc, int lz, int dplane) {
     const int b = lz * acc.LW + cell + 1, rc = lz * acc.NW + cell + 1;
 #pragma unroll
@@ -598,41 +598,83 @@ __device__ __forceinline__ void deposit_one(const AccLds &acc, int o, int rc, T 
   }
 }
 
-// LDS layout of the particle kernel (byte offsets): the moment accumulators of the tile and its
-// halo (delta-j and density per node, S-hat scalars per corner of the tile's cells and their
-// one-cell ring), the fields the tile's particles read (E-bar on the tile's nodes, H^{n+1/2} on
-// its cells, H^{n+3/2} on its cells plus the ring), the per-wave mover queues, per species the
-// int move counters of the tile's cells and the arrival counts of the tile's cells and their
-// ring, and the first and end slot of every tile row of every species slot.  Accumulators are FP64; fields and queues use the
-// kernel's arithmetic type.
+// Chunk-of-2 form: a particle whose new cell (gi, gk) lies outside the tile adds its moments to
+// the global moment planes at once, at the cell's 4 corner nodes: the same products as an LDS
+// deposit, with S-hat expanded with that cell's B as the fold expands the per-cell sums.  At
+// a few particles per cell about one in three hundred leaves its tile in a cycle, and the
+// tile's LDS then holds the nodes and cells of the tile alone.
+template <typename T>
+__device__ void deposit_global(const StepArgs &a, int gi, int gk, T fx, T fz, const Compact<T> &m,
+                               T w, T B0t, T B1t, T B2t, int dplane) {
+  const GridArgs &g = a.g;
+  const int64_t nn = g.nnodes;
+  const int gi1 = (g.bc_x == PIC_BC_PERIODIC && gi + 1 == g.nx) ? 0 : gi + 1;
+  const int gk1 = gk + 1 == g.nz ? 0 : gk + 1;
+#pragma unroll 1
+  for (int c = 0; c < 4; ++c) {
+    const int cx = c & 1, cz = c >> 1;
+    const T W = (cx ? fx : T(1) - fx) * (cz ? fz : T(1) - fz);
+    const double A0 = (double)(W * m.a0), A1 = (double)(W * m.a1), A2 = (double)(W * m.a2);
+    const double B0 = (double)B0t, B1 = (double)B1t, B2 = (double)B2t;
+    double *M = a.M + ((int64_t)(cz ? gk1 : gk) * g.nxn + (cx ? gi1 : gi));
+    unsafeAtomicAdd(M, fma(A2, B0 * B0, A0));
+    unsafeAtomicAdd(M + nn, fma(A2, B0 * B1, A1 * B2));
+    unsafeAtomicAdd(M + 2 * nn, fma(A2, B0 * B2, -A1 * B1));
+    unsafeAtomicAdd(M + 3 * nn, fma(A2, B1 * B0, -A1 * B2));
+    unsafeAtomicAdd(M + 4 * nn, fma(A2, B1 * B1, A0));
+    unsafeAtomicAdd(M + 5 * nn, fma(A2, B1 * B2, A1 * B0));
+    unsafeAtomicAdd(M + 6 * nn, fma(A2, B2 * B0, A1 * B1));
+    unsafeAtomicAdd(M + 7 * nn, fma(A2, B2 * B1, -A1 * B0));
+    unsafeAtomicAdd(M + 8 * nn, fma(A2, B2 * B2, A0));
+    unsafeAtomicAdd(M + 9 * nn, (double)(W * m.j0));
+    unsafeAtomicAdd(M + 10 * nn, (double)(W * m.j1));
+    unsafeAtomicAdd(M + 11 * nn, (double)(W * m.j2));
+    unsafeAtomicAdd(M + (9 + dplane) * nn, (double)(W * w));
+    if (a.mflag) a.mflag[((int64_t)(cz ? gk1 : gk) * g.nxn + (cx ? gi1 : gi)) / kFlagNodes] = 1;
+  }
+}
+
+// LDS layout of the particle kernel (byte offsets): the moment accumulators (delta-j and
+// density per node, S-hat scalars per cell corner), the fields the tile's particles read (E-bar
+// on the tile's nodes, H^{n+1/2} on its cells, H^{n+3/2} on its cells plus the one-cell ring a
+// particle can move into), the per-wave mover queues, per species the int move counters of the
+// tile's cells and the arrival counts of the tile's cells and their ring, and the first and
+// end slot of every tile row of every species slot.  Two layouts: with mover queues
+// (qwords > 0) the accumulators cover the tile and its ring; without (the chunk-of-2 form) they
+// cover the tile's own nodes and cells, particles leaving the tile deposit to the global
+// planes, and the arrivals are summed from the move counters (no arrival array), which brings
+// a 32 x 4 tile of two species to 40 KB: four blocks per CU.  Accumulators are FP64; fields
+// and queues use the kernel's arithmetic type.
 struct TileLds {
-  int LW, LH, plane;          // accumulator node grid (tx + 3) x (tz + 3)
+  int LW, LH, plane;          // accumulator node grid (tx + 3) x (tz + 3), or (tx + 1) x (tz + 1)
   int EW, EPL;                // E-bar node grid (tx + 1) x (tz + 1)
   int HPL;                    // H^{n+1/2} cells tx x tz
   int NW, NPL;                // H^{n+3/2} cells (tx + 2) x (tz + 2)
+  int CPL;                    // cells of the S-hat corner planes: NPL or HPL
   int n_node;                 // node accumulator planes: 3 + species
   size_t acc, accc, eb, ho, hn, mq, cnt, arr, rows;  // byte offsets
   size_t bytes;
   __host__ __device__ TileLds(int n_planes, int tx, int tz, int tsize, int qwords) {
-    LW = tx + 3;
-    LH = tz + 3;
+    const int ring = qwords ? 1 : 0;
+    LW = tx + 1 + 2 * ring;
+    LH = tz + 1 + 2 * ring;
     plane = LW * LH;
     EW = tx + 1;
     EPL = EW * (tz + 1);
     HPL = tx * tz;
     NW = tx + 2;
     NPL = NW * (tz + 2);
+    CPL = ring ? NPL : HPL;
     n_node = 3 + (n_planes - 12);
     acc = 0;
     accc = acc + (size_t)n_node * plane * sizeof(double);
-    eb = accc + (size_t)12 * NPL * sizeof(double);
+    eb = accc + (size_t)12 * CPL * sizeof(double);
     ho = eb + 3 * (size_t)EPL * tsize;
     hn = ho + 3 * (size_t)HPL * tsize;
     mq = (hn + 3 * (size_t)NPL * tsize + 7) & ~(size_t)7;
-    // qwords 0: no mover queues (the kernel form that deposits every particle at once)
     cnt = mq + (qwords ? (size_t)(kBlock / 64) * kMqCap * ((size_t)qwords * tsize + 2 * sizeof(int)) : 0);
     arr = cnt + (size_t)(n_node - 3) * tx * tz * kMoveCodes * sizeof(int);
-    rows = arr + (size_t)(n_node - 3) * (tx + 2) * (tz + 2) * sizeof(int);
+    rows = arr + (ring ? (size_t)(n_node - 3) * (tx + 2) * (tz + 2) * sizeof(int) : 0);
     bytes = rows + (size_t)(n_node - 3) * tz * 2 * sizeof(int);
   }
 };
@@ -700,7 +742,10 @@ struct Pstate<true> {
 // density times its own density, which is read with the state and written with the pushed
 // state (a species with one density reads it from a one-element array with stride 0).  CH is
 // the chunk of particles a lane loads at once: 4, or 2 where a lane holds about two particles
-// per row (fewer registers and instructions when the chunk would be half empty).
+// per row.  The chunk-of-2 form deposits each particle into LDS at once (no register sums or
+// mover queue), reads the fields for every particle, keeps accumulators for the tile's own
+// nodes and cells only and sends the moments of a particle that leaves the tile to the global
+// planes: about 120 VGPRs (FP64) and 40 KB of LDS at 32 x 4, four blocks per CU.
 template <bool PUSH, bool MIXED, bool IDS, bool PW, int CH = 4>
 __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
   using T = typename std::conditional<MIXED, float, double>::type;
@@ -717,22 +762,26 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
   constexpr int kQw = mq_words(PW);
   const TileLds Lo(g.n_planes, t.tx, t.tz, (int)sizeof(T), (PUSH && CH == 2) ? 0 : kQw);
   const AccLds acc{reinterpret_cast<double *>(ldsb + Lo.acc),
-                   reinterpret_cast<double *>(ldsb + Lo.accc), Lo.plane, Lo.NPL, Lo.LW, Lo.NW};
+                   reinterpret_cast<double *>(ldsb + Lo.accc), Lo.plane, Lo.CPL, Lo.LW, Lo.NW};
   T *Eb = reinterpret_cast<T *>(ldsb + Lo.eb);
   T *Ho = reinterpret_cast<T *>(ldsb + Lo.ho);
   T *Hn = reinterpret_cast<T *>(ldsb + Lo.hn);
   int *cntL = reinterpret_cast<int *>(ldsb + Lo.cnt);
-  int *arrL = reinterpret_cast<int *>(ldsb + Lo.arr);
+  int *arrL = reinterpret_cast<int *>(ldsb + Lo.arr);  // the layout with the ring
   const int LW = Lo.LW, plane = Lo.plane;
-  const int n_acc = Lo.n_node * plane + 12 * Lo.NPL;  // node planes, then cell-corner planes
+  const int n_acc = Lo.n_node * plane + 12 * Lo.CPL;  // node planes, then cell-corner planes
 
   for (int e = threadIdx.x; e < n_acc; e += blockDim.x) acc.node[e] = 0.0;
+  // the chunk-of-2 form: accumulators over the tile's own nodes and cells (no ring)
+  constexpr bool kTileOnly = PUSH && CH == 2;
   const int AW = t.tx + 2, AH = t.tz + 2;  // arrival counts: the tile's cells and their ring
   if (PUSH) {
     const int nsl = Lo.n_node - 3;
     for (int e = threadIdx.x; e < nsl * ntc * kMoveCodes; e += blockDim.x) cntL[e] = 0;
-    for (int e = threadIdx.x; e < nsl * AW * AH; e += blockDim.x) arrL[e] = 0;
+    if constexpr (!kTileOnly)
+      for (int e = threadIdx.x; e < nsl * AW * AH; e += blockDim.x) arrL[e] = 0;
   }
+  const int cw = i1 - i0, chh = k1 - k0;  // the tile's cells inside the grid
   // a tile and its two-cell ring fit in the grid along an axis: wraps need one compare there
   const bool nearx = g.nx >= t.tx + 3, nearz = g.nz >= t.tz + 3;
   // Stage the fields of the tile and the slot range of every tile row of every species in one
@@ -950,7 +999,9 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
           // On entering a new cell: read its fields, use them, and only then flush the previous
           // cell's accumulator.  LDS operations complete in order, so a read issued after the
           // flush's atomics (or consumed while they are in flight) would wait for all of them.
-          const bool newcell = ok && li != ca.cell;
+          // The chunk-of-2 form reads them for every particle (a lane holds about two per row,
+          // and fields kept across particles would hold about 30 registers).
+          const bool newcell = kDirect || (ok && li != ca.cell);
           if (newcell) {
             fB0 = Ho[hc];
             fB1 = Ho[Lo.HPL + hc];
@@ -1062,6 +1113,9 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
               // of the new cell (read before any LDS atomic of this particle is issued)
               const int hn = (lk + dk + 1) * Lo.NW + (li + di + 1);
               m = compact_moments(K, rg1, n0, n1, n2, Hn[hn], Hn[Lo.NPL + hn], Hn[2 * Lo.NPL + hn]);
+              // the new cell, tile-local (a dead particle stays, unused)
+              const int ldx = li + di, ldz = lk + dk;
+              const bool inside = ldx >= 0 && ldx < cw && ldz >= 0 && ldz < chh;
               if constexpr (PW) scale_compact(m, wp);
               if constexpr (MIXED) {
                 fx2 = xn;
@@ -1110,10 +1164,14 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
                 if (code != kAbsorbed) atomicAdd(&cntS[hc * kMoveCodes + code], 1);
               }
               // stayers add to the lane's accumulator, movers go through the queue (with few
-              // particles per lane every particle goes to the LDS accumulators at once)
-              if (kDirect) {
-                if (alive)
-                  deposit_one(acc, (lz + dk) * LW + (li + 1 + di), hn, fx2, fz2, m, wp, dplane);
+              // particles per lane every particle goes to the LDS accumulators at once, or to
+              // the global planes if it leaves the tile)
+              if constexpr (kDirect) {
+                if (alive && inside)
+                  deposit_one(acc, ldz * LW + ldx, ldz * t.tx + ldx, fx2, fz2, m, wp, dplane);
+                if (alive && !inside)
+                  deposit_global(a, i2, k2, fx2, fz2, m, wp, Hn[hn], Hn[Lo.NPL + hn],
+                                 Hn[2 * Lo.NPL + hn], dplane);
               } else if (alive && code == 4u) {
                 ca.add(fx2, fz2, m, wp);
               } else if (alive) {
@@ -1158,11 +1216,8 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
     }
   }
   __syncthreads();
-  // Move counts of the tile's cells (for the ranking), and the particles they send to each cell
-  // of the tile and its ring, summed in LDS (added to the per-cell arrival counts after the
-  // fold: the sort's scan reads those instead of gathering nine counts per cell).  The counts
-  // of every species are kept until here, so the species need no barriers between them.
-  const int cw = i1 - i0, chh = k1 - k0;
+  // Move counts of the tile's cells, for the ranking.  The counts of every species are kept
+  // until here, so the species need no barriers between them.
   for (int s = 0; s < a.nsp; ++s) {
     const SpeciesArgs &sp = a.sp[s];
     if (!PUSH || !sp.active) continue;
@@ -1183,7 +1238,7 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
           if (!a.count_masks || v) sp.cnt[(int64_t)d * nc + cg] = v;
           if (v) {
             mask |= 1u << d;
-            atomicAdd(&arrS[(lkk + d / 3) * AW + (li + d % 3)], v);
+            if constexpr (!kTileOnly) atomicAdd(&arrS[(lkk + d / 3) * AW + (li + d % 3)], v);
           }
         }
         if (a.count_masks) sp.cmask[cg] = (uint16_t)mask;
@@ -1194,14 +1249,14 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
   // delta-j and the densities as they are; S-hat from the S-hat scalars of the (up to) four
   // cells around the node, each expanded with its cell's B (H^{n+3/2} after a push, H^{n+1/2}
   // for a deposit of the current state): S-hat = a0 I + a1 [B]x + a2 B B^T.
-  const int NH = t.tz + 2;
   const SmallDiv div_lw(LW);
   for (int idx = threadIdx.x; idx < plane; idx += blockDim.x) {
     const int lzz = div_lw.q(idx), lx = idx - lzz * LW;
-    int gx = i0 - 1 + lx;
+    constexpr int kOff = kTileOnly ? 0 : 1;  // the ring's column and row before the tile
+    int gx = i0 - kOff + lx;
     bool in = true;
     if (g.bc_x == PIC_BC_PERIODIC) gx = wrap_t(gx, g.nx, nearx); else in = gx >= 0 && gx <= g.nx;
-    const int gz = wrap_t(k0 - 1 + lzz, g.nz, nearz);
+    const int gz = wrap_t(k0 - kOff + lzz, g.nz, nearz);
     const int64_t node = (int64_t)gz * g.nxn + gx;
     // the field solve reads and clears the moment planes only under a set deposit flag: set
     // the flag of every node this fold adds to
@@ -1218,20 +1273,22 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
     bool any = false;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const int rx = lx - (c & 1), rz = lzz - (c >> 1);  // the cell whose corner c is this node
-      if (rx < 0 || rx >= Lo.NW || rz < 0 || rz >= NH) continue;
-      const int rc = rz * Lo.NW + rx;
-      const double A0 = acc.cell[(0 * 4 + c) * Lo.NPL + rc];
-      const double A1 = acc.cell[(1 * 4 + c) * Lo.NPL + rc];
-      const double A2 = acc.cell[(2 * 4 + c) * Lo.NPL + rc];
+      // the cell whose corner c is this node, tile-local (-1 and tx, tz: the ring)
+      const int cx = lx - kOff - (c & 1), cz = lzz - kOff - (c >> 1);
+      if (cx < -kOff || cx >= t.tx + kOff || cz < -kOff || cz >= t.tz + kOff) continue;
+      const int rc = (cz + 1) * Lo.NW + (cx + 1);                 // in the ring's numbering
+      const int ac = kTileOnly ? cz * t.tx + cx : rc;             // in the corner planes
+      const double A0 = acc.cell[(0 * 4 + c) * Lo.CPL + ac];
+      const double A1 = acc.cell[(1 * 4 + c) * Lo.CPL + ac];
+      const double A2 = acc.cell[(2 * 4 + c) * Lo.CPL + ac];
       if (A0 == 0.0 && A1 == 0.0 && A2 == 0.0) continue;
       double B0 = 0.0, B1 = 0.0, B2 = 0.0;
       if (PUSH) {
         B0 = (double)Hn[rc];
         B1 = (double)Hn[Lo.NPL + rc];
         B2 = (double)Hn[2 * Lo.NPL + rc];
-      } else if (rx >= 1 && rx <= t.tx && rz >= 1 && rz <= t.tz) {
-        const int hc = (rz - 1) * t.tx + (rx - 1);
+      } else if (cx >= 0 && cx < t.tx && cz >= 0 && cz < t.tz) {
+        const int hc = cz * t.tx + cx;
         B0 = (double)Ho[hc];
         B1 = (double)Ho[Lo.HPL + hc];
         B2 = (double)Ho[2 * Lo.HPL + hc];
@@ -1259,15 +1316,29 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
     if (wrote && a.mflag) a.mflag[node / kFlagNodes] = 1;
   }
   if (PUSH) {
-    __syncthreads();
+    // The particles the tile's cells send to each cell of the tile and its ring (the cell
+    // (x - dx, z - dz) sends count[code (dx, dz)]), added to the per-cell arrival counts: the
+    // sort's scan reads those instead of gathering nine counts per cell.
+    // (the layout with the ring sums them in LDS during the count pass)
+    if constexpr (!kTileOnly) __syncthreads();
     for (int s = 0; s < a.nsp; ++s) {
       const SpeciesArgs &sp = a.sp[s];
       if (!sp.active) continue;
+      const int *cntS = cntL + s * ntc * kMoveCodes;
       const int *arrS = arrL + s * AW * AH;
       for (int e = threadIdx.x; e < AW * AH; e += blockDim.x) {
-        const int v = arrS[e];
-        if (v == 0) continue;
         const int az = SmallDiv(AW).q(e), ax = e - az * AW;
+        int v = 0;
+        if constexpr (kTileOnly) {
+#pragma unroll
+          for (int d = 0; d < kMoveCodes; ++d) {
+            const int sx = ax - d % 3, sz = az - d / 3;  // the source cell, tile-local
+            if (sx >= 0 && sx < cw && sz >= 0 && sz < chh) v += cntS[(sz * t.tx + sx) * kMoveCodes + d];
+          }
+        } else {
+          v = arrS[e];
+        }
+        if (v == 0) continue;
         int gi = i0 - 1 + ax;
         const int gk = wrap1(k0 - 1 + az, g.nz);
         if (g.bc_x == PIC_BC_PERIODIC) gi = wrap1(gi, g.nx);
@@ -1278,10 +1349,11 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
 }
 
 // Waves per SIMD: the register sums of the chunks of 4 hold two FP64 waves (three mixed); the
-// chunk-of-2 form, without them, holds one more.
+// chunk-of-2 form, without them, holds four in both precisions (at 32 x 4 cells and two
+// species its LDS also lets four blocks share a CU).
 template <bool PUSH, bool MIXED, bool IDS, bool PW, int CH = 4>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(2 + MIXED + (CH == 2), 2 + MIXED + (CH == 2))))
+__attribute__((amdgpu_waves_per_eu(CH == 2 ? 4 : 2 + MIXED, CH == 2 ? 4 : 2 + MIXED)))
 void k_particles(const StepArgs a) {
   // clear the next order's tile flags (set by the scan of this cycle's sort); the grid has a
   // block for every tile index
