@@ -416,18 +416,18 @@ template <typename T>
 __device__ __forceinline__ Compact<T> compact_moments(const SpConst<T> &k, T ginv, T u0, T u1,
                                                       T u2, T B0, T B1, T B2) {
   const T s = k.beta * ginv;
-  const T BB = B0 * B0 + B1 * B1 + B2 * B2;
+  const T BB = fmaT(B2, B2, fmaT(B1, B1, B0 * B0));
   const T inv = rcpT(fmaT(s * s, BB, T(1)));
   Compact<T> m;
   m.a0 = k.cS * ginv * inv;
   m.a1 = m.a0 * s;
   m.a2 = m.a1 * s;
   const T kk = k.kJ * ginv * inv;
-  const T bu = B0 * u0 + B1 * u1 + B2 * u2;
+  const T bu = fmaT(B2, u2, fmaT(B1, u1, B0 * u0));
   const T s2bu = s * s * bu;
-  m.j0 = kk * fmaT(s2bu, B0, fmaT(s, u1 * B2 - u2 * B1, u0));
-  m.j1 = kk * fmaT(s2bu, B1, fmaT(s, u2 * B0 - u0 * B2, u1));
-  m.j2 = kk * fmaT(s2bu, B2, fmaT(s, u0 * B1 - u1 * B0, u2));
+  m.j0 = kk * fmaT(s2bu, B0, fmaT(s, fmaT(u1, B2, -(u2 * B1)), u0));
+  m.j1 = kk * fmaT(s2bu, B1, fmaT(s, fmaT(u2, B0, -(u0 * B2)), u1));
+  m.j2 = kk * fmaT(s2bu, B2, fmaT(s, fmaT(u0, B1, -(u1 * B0)), u2));
   return m;
 }
 
@@ -1019,7 +1019,7 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
             }
           }
           const T one = T(1);
-          const T ginv = rsqT(one + u0 * u0 + u1 * u1 + u2 * u2);  // 1 / gamma(u^n)
+          const T ginv = rsqT(fmaT(u2, u2, fmaT(u1, u1, fmaT(u0, u0, one))));  // 1 / gamma(u^n)
           if (!PUSH) {
             Compact<T> m0 = compact_moments(K, ginv, u0, u1, u2, fB0, fB1, fB2);
             if constexpr (PW) scale_compact(m0, wp);
@@ -1041,19 +1041,20 @@ __device__ __forceinline__ void particles_body(const StepArgs &a, int tile) {
               T Ep[3];
 #pragma unroll
               for (int qq = 0; qq < 3; ++qq)
-                Ep[qq] = W0 * fE[4 * qq] + W1 * fE[4 * qq + 1] + W2 * fE[4 * qq + 2] + W3 * fE[4 * qq + 3];
+                Ep[qq] = fmaT(W3, fE[4 * qq + 3],
+                              fmaT(W2, fE[4 * qq + 2], fmaT(W1, fE[4 * qq + 1], W0 * fE[4 * qq])));
               // implicit push: with a = u + beta E and b = beta B / gamma,
               // u-bar = R a = (a + a x b + (a.b) b) / (1 + b.b), and u' = 2 u-bar - u
               const T bg = K.beta * ginv;
               const T bx = bg * fB0, by = bg * fB1, bz = bg * fB2;
               const T a0 = fmaT(K.beta, Ep[0], u0), a1 = fmaT(K.beta, Ep[1], u1);
               const T a2 = fmaT(K.beta, Ep[2], u2);
-              const T inv = rcpT(one + bx * bx + by * by + bz * bz);
-              const T ab = a0 * bx + a1 * by + a2 * bz;
-              const T n0 = T(2) * ((a0 + (a1 * bz - a2 * by) + ab * bx) * inv) - u0;
-              const T n1 = T(2) * ((a1 + (a2 * bx - a0 * bz) + ab * by) * inv) - u1;
-              const T n2 = T(2) * ((a2 + (a0 * by - a1 * bx) + ab * bz) * inv) - u2;
-              const T g1sq = one + n0 * n0 + n1 * n1 + n2 * n2;
+              const T inv = rcpT(fmaT(bz, bz, fmaT(by, by, fmaT(bx, bx, one))));
+              const T ab = fmaT(a2, bz, fmaT(a1, by, a0 * bx));
+              const T n0 = fmaT(T(2), fmaT(ab, bx, a0 + fmaT(a1, bz, -(a2 * by))) * inv, -u0);
+              const T n1 = fmaT(T(2), fmaT(ab, by, a1 + fmaT(a2, bx, -(a0 * bz))) * inv, -u1);
+              const T n2 = fmaT(T(2), fmaT(ab, bz, a2 + fmaT(a0, by, -(a1 * bx))) * inv, -u2);
+              const T g1sq = fmaT(n2, n2, fmaT(n1, n1, fmaT(n0, n0, one)));
               const T rg1 = rsqT(g1sq);  // 1 / gamma(u^{n+1})
               const T vx = n0 * rg1, vz = n2 * rg1;
               // position advance: FP64 in cell units; mixed as FP32 offset with integer carry
