@@ -737,7 +737,7 @@ struct Pstate<true> {
 // MIXED selects the mixed-precision form: FP32 state, gather, push and per-lane partial sums,
 // added into FP64 LDS accumulators and the FP64 moment planes.  With chunks of 4 the FP64 form
 // needs about 230 VGPRs (two waves per SIMD) and the FP32 form about 150 (three); the
-// chunk-of-2 form needs about 130 and 105.  IDS adds the copy of particle ids
+// chunk-of-2 form needs about 120 and 105 (four).  IDS adds the copy of particle ids
 // (tests only).  PW selects per-particle densities: each particle's moments are those of unit
 // density times its own density, which is read with the state and written with the pushed
 // state (a species with one density reads it from a one-element array with stride 0).  CH is
