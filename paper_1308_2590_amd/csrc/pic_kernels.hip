@@ -650,7 +650,7 @@ struct TileLds {
   int EW, EPL;                // E-bar node grid (tx + 1) x (tz + 1)
   int HPL;                    // H^{n+1/2} cells tx x tz
   int NW, NPL;                // H^{n+3/2} cells (tx + 2) x (tz + 2)
-  int CPL;                    // cells of the S-hat corner planes: NPL or HPL
+  int CPL;                    // pitch of the S-hat corner planes: NPL, or HPL padded
   int n_node;                 // node accumulator planes: 3 + species
   size_t acc, accc, eb, ho, hn, mq, cnt, arr, rows;  // byte offsets
   size_t bytes;
@@ -664,7 +664,9 @@ struct TileLds {
     HPL = tx * tz;
     NW = tx + 2;
     NPL = NW * (tz + 2);
-    CPL = ring ? NPL : HPL;
+    // without the ring the corner-plane pitch is padded to 4 (mod 8) doubles: the two lanes of
+    // one cell, whose corners are two planes apart, then use complementary LDS banks
+    CPL = ring ? NPL : HPL + ((4 - HPL % 8) + 8) % 8;
     n_node = 3 + (n_planes - 12);
     acc = 0;
     accc = acc + (size_t)n_node * plane * sizeof(double);
