@@ -220,8 +220,9 @@ pic_status pic_profile_read(pic_ctx *ctx, pic_profile *out);
 /* Select the mover options (PIC_MOVER_* bits; 0 restores the default mover).  Both the
  * deposit (Step 1) and the push of every later cycle use them.  With any option set, the
  * particle stage of a cycle runs in a kernel with one thread per particle that deposits each
- * particle's expanded moments with global atomics (per-particle B makes S-hat differ from
- * particle to particle): slower than the default tile kernel.  If particles are loaded, the
+ * particle's expanded moments with global atomics, summed first over the lanes of a wavefront
+ * that share a cell (per-particle B makes S-hat differ from particle to particle): about three
+ * times slower than the default tile kernel.  If particles are loaded, the
  * moments of the current state are deposited again with the new options.  Errors:
  * PIC_ERR_ARG (unknown bits, or a mixed-precision context: the options are FP64 only),
  * PIC_ERR_STATE (the context is in a batch). */

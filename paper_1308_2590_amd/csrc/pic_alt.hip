@@ -6,8 +6,9 @@
 //                    gamma-bar (gamma(u^n), or gamma(u^n + beta E^n) with E^n interpolated at
 //                    the particle), the implicit push of Eq. (2), position advance and move
 //                    code, then the deposit of S-hat, delta-j and density (Step 1, Eq. (3)) at
-//                    the new position with the same options, straight into the global moment
-//                    planes with FP64 atomics.  It writes the move codes, counts and arrivals
+//                    the new position with the same options, into the global moment planes with
+//                    FP64 atomics, each first summed over the lanes of a wavefront that
+//                    deposit into the same cell.  It writes the move codes, counts and arrivals
 //                    the cycle's sort reads, exactly as the tile kernel does.  Without push it
 //                    deposits the current state.
 //   k_energy         field energy (1/2)(sum |E|^2 over nodes + sum |H|^2 over cells) dx dz and
@@ -91,13 +92,12 @@ __device__ double gamma_bar(const GridArgs &g, const double *En, int mover, doub
   return sqrt(1.0 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
 }
 
-// Deposit one particle's S-hat (9), delta-j (3) and density at its corner nodes: with
-// s = beta / gamma-bar and D = 1 + s^2 B.B, S-hat = (w q^2 dt^2 / (4 m gamma-bar D)) (I + s [B]x
-// + s^2 B B^T) and delta-j = (w q / (gamma-bar D)) (u + s u x B + s^2 (B.u) B), w the
-// particle's density (wp when the species carries one per particle).
-__device__ void deposit_one(const StepArgs &a, const SpeciesArgs &sp, int s, double gam,
-                            const double u[3], const double B[3], const int64_t node[4],
-                            const double W[4], double wp) {
+// One particle's S-hat (9), delta-j (3) and density: with s = beta / gamma-bar and
+// D = 1 + s^2 B.B, S-hat = (w q^2 dt^2 / (4 m gamma-bar D)) (I + s [B]x + s^2 B B^T) and
+// delta-j = (w q / (gamma-bar D)) (u + s u x B + s^2 (B.u) B), w the particle's density (wp
+// when the species carries one per particle).
+__device__ void moments13(const SpeciesArgs &sp, double gam, const double u[3], const double B[3],
+                          double wp, double v[13]) {
   const double sg = sp.beta / gam;
   const double inv = 1.0 / (1.0 + sg * sg * (B[0] * B[0] + B[1] * B[1] + B[2] * B[2]));
   const double cS = sp.w_stride ? sp.cS1 * wp : sp.cS;
@@ -105,7 +105,6 @@ __device__ void deposit_one(const StepArgs &a, const SpeciesArgs &sp, int s, dou
   const double a0 = cS / gam * inv, a1 = a0 * sg, a2 = a1 * sg;
   const double kk = kJ / gam * inv;
   const double bu = B[0] * u[0] + B[1] * u[1] + B[2] * u[2];
-  double v[13];
   v[0] = a2 * B[0] * B[0] + a0;
   v[1] = a2 * B[0] * B[1] + a1 * B[2];
   v[2] = a2 * B[0] * B[2] - a1 * B[1];
@@ -119,11 +118,38 @@ __device__ void deposit_one(const StepArgs &a, const SpeciesArgs &sp, int s, dou
   v[10] = kk * (u[1] + sg * (u[2] * B[0] - u[0] * B[2]) + sg * sg * bu * B[1]);
   v[11] = kk * (u[2] + sg * (u[0] * B[1] - u[1] * B[0]) + sg * sg * bu * B[2]);
   v[12] = sp.w_stride ? wp : sp.w;
-  const int64_t nn = a.g.nnodes;
-  for (int c = 0; c < 4; ++c) {
-    for (int r = 0; r < 12; ++r) unsafeAtomicAdd(&a.M[(int64_t)r * nn + node[c]], W[c] * v[r]);
-    unsafeAtomicAdd(&a.M[(int64_t)(12 + s) * nn + node[c]], W[c] * v[12]);
+}
+
+// The threads of a wavefront follow the cell-sorted order, so lanes that add to the same
+// addresses (one cell's nodes, counter or arrival count) are neighbours.  Their values are
+// summed over each run of equal keys (a segmented reduction towards the run's first lane) and
+// the first lane issues one global atomic per value: same-address atomics from the lanes of
+// one cell would otherwise be serialised.  All 64 lanes take part; a lane without a value has
+// a key of its own (negative).
+struct Seg {
+  int lane, seg_end, steps;
+  bool head;
+};
+
+__device__ __forceinline__ Seg seg_of(int64_t key) {
+  const int lane = threadIdx.x & 63;
+  const int64_t prev = __shfl_up(key, 1, 64);
+  const bool head = lane == 0 || prev != key;
+  const uint64_t heads = __ballot(head);
+  const uint64_t above = heads & ~((2ull << lane) - 1ull);
+  Seg sg{lane, above ? __ffsll((unsigned long long)above) - 1 : 64, 0, head};
+  while (sg.steps < 6 && __any(lane + (1 << sg.steps) < sg.seg_end)) ++sg.steps;
+  return sg;
+}
+
+template <typename V>
+__device__ __forceinline__ V seg_sum(const Seg &sg, V v) {
+  for (int q = 0; q < sg.steps; ++q) {
+    const int d = 1 << q;
+    const V t = __shfl_down(v, d, 64);
+    if (sg.lane + d < sg.seg_end) v += t;
   }
+  return v;
 }
 
 template <bool PUSH>
@@ -143,88 +169,118 @@ __global__ __launch_bounds__(kBlock) void k_particles_alt(const StepArgs a, int 
   if (!sp.active) return;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = sp.cs[g.ncells];
-  if (j >= n) return;
-  const int p = sp.perm[j];
-  const double x = sp.src[0][p], z = sp.src[1][p];
-  const double u[3] = {sp.src[2][p], sp.src[3][p], sp.src[4][p]};
-  const double wp = sp.w_stride ? sp.src_w[p] : sp.w;
-  const int i = (int)floor(x), k = (int)floor(z);
-  if (i < 0 || i >= g.nx || k < 0 || k >= g.nz) {
-    atomicOr(a.flags, kFlagOrderA);
-    if (PUSH) sp.locode[j] = ((uint32_t)j << 4) | kAbsorbed;
-    return;
+  if ((int)(blockIdx.x * blockDim.x) >= n) return;  // the whole block past the particles
+  const int lane = threadIdx.x & 63;
+  // what the lane adds: moments at 4 nodes (dep), a move count (cnt_on), an arrival
+  bool dep = false, cnt_on = false;
+  int64_t dkey = 0, ckey = 0, cidx = 0;
+  int64_t node[4] = {0, 0, 0, 0};
+  double W[4] = {0.0, 0.0, 0.0, 0.0}, v[13];
+  for (int r = 0; r < 13; ++r) v[r] = 0.0;
+  if (j < n) {
+    const int p = sp.perm[j];
+    const double x = sp.src[0][p], z = sp.src[1][p];
+    const double u[3] = {sp.src[2][p], sp.src[3][p], sp.src[4][p]};
+    const double wp = sp.w_stride ? sp.src_w[p] : sp.w;
+    const int i = (int)floor(x), k = (int)floor(z);
+    if (i < 0 || i >= g.nx || k < 0 || k >= g.nz) {
+      atomicOr(a.flags, kFlagOrderA);
+      if (PUSH) sp.locode[j] = ((uint32_t)j << 4) | kAbsorbed;
+    } else {
+      corners(g, i, k, x - (double)i, z - (double)k, node, W);
+      double B[3];
+      b_at(g, a.Hold, mover, x, z, i, k, B);
+      const double gam = gamma_bar(g, a.Eold, mover, sp.beta, u, node, W);
+      if (!PUSH) {
+        moments13(sp, gam, u, B, wp, v);
+        dep = true;
+        dkey = (int64_t)k * g.nx + i;
+      } else {
+        // E-bar at the particle and the implicit push: a = u + beta E-bar, b = beta B / gamma-bar,
+        // u-bar = (a + a x b + (a.b) b) / (1 + b.b), u' = 2 u-bar - u
+        const int64_t nn = g.nnodes;
+        double Eb[3];
+        for (int r = 0; r < 3; ++r) {
+          const double *eo = a.Eold + r * nn, *en = a.Enew + r * nn;
+          double acc = 0.0;
+          for (int c = 0; c < 4; ++c) acc += W[c] * (0.5 * (eo[node[c]] + en[node[c]]));
+          Eb[r] = acc;
+        }
+        const double bx = sp.beta / gam * B[0], by = sp.beta / gam * B[1], bz = sp.beta / gam * B[2];
+        const double a0 = u[0] + sp.beta * Eb[0], a1 = u[1] + sp.beta * Eb[1], a2 = u[2] + sp.beta * Eb[2];
+        const double inv = 1.0 / (1.0 + bx * bx + by * by + bz * bz);
+        const double ab = a0 * bx + a1 * by + a2 * bz;
+        double un[3];
+        un[0] = 2.0 * ((a0 + (a1 * bz - a2 * by) + ab * bx) * inv) - u[0];
+        un[1] = 2.0 * ((a1 + (a2 * bx - a0 * bz) + ab * by) * inv) - u[1];
+        un[2] = 2.0 * ((a2 + (a0 * by - a1 * bx) + ab * bz) * inv) - u[2];
+        const double g1 = sqrt(1.0 + un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
+        double xn = x + g.cx * (un[0] / g1), zn = z + g.cz * (un[2] / g1);
+        bool alive = true;
+        if (g.bc_x == PIC_BC_PERIODIC) {
+          if (xn < 0.0) xn += (double)g.nx;
+          if (xn >= (double)g.nx) xn -= (double)g.nx;
+        } else if (xn < 0.0 || xn >= (double)g.nx) {
+          alive = false;
+        }
+        if (zn < 0.0) zn += (double)g.nz;
+        if (zn >= (double)g.nz) zn -= (double)g.nz;
+        const bool finite = isfinite(g1) && isfinite(xn) && isfinite(zn);
+        if (!finite) atomicOr(a.flags, kFlagNonFiniteA);
+        alive = alive && finite;
+        const int i2 = finite ? (int)floor(xn) : i, k2 = finite ? (int)floor(zn) : k;
+        int di = i2 - i, dk = k2 - k;
+        if (di > 1) di -= g.nx;
+        if (di < -1) di += g.nx;
+        if (dk > 1) dk -= g.nz;
+        if (dk < -1) dk += g.nz;
+        const bool jump = di < -1 || di > 1 || dk < -1 || dk > 1;
+        if (alive && jump) atomicOr(a.flags, kFlagJumpA);
+        alive = alive && !jump;
+        const uint32_t code = alive ? (uint32_t)((dk + 1) * 3 + (di + 1)) : kAbsorbed;
+        // the pushed state goes to location j of the other buffer; the sort reads the codes
+        sp.dst[0][j] = xn;
+        sp.dst[1][j] = zn;
+        sp.dst[2][j] = un[0];
+        sp.dst[3][j] = un[1];
+        sp.dst[4][j] = un[2];
+        if (sp.dst_id) sp.dst_id[j] = sp.src_id[p];
+        if (sp.w_stride) sp.dst_w[j] = wp;
+        sp.locode[j] = ((uint32_t)j << 4) | code;
+        if (alive) {
+          const int64_t src_cell = (int64_t)k * g.nx + i;
+          cnt_on = true;
+          ckey = (src_cell << 4) | code;
+          cidx = (int64_t)code * g.ncells + src_cell;
+          // the moments at x^{n+3/2} with u^{n+1}, B = H^{n+3/2} at the new position and
+          // E^{n+1}
+          corners(g, i2, k2, xn - (double)i2, zn - (double)k2, node, W);
+          double B2[3];
+          b_at(g, a.Hnew, mover, xn, zn, i2, k2, B2);
+          const double gam2 = gamma_bar(g, a.Enew, mover, sp.beta, un, node, W);
+          moments13(sp, gam2, un, B2, wp, v);
+          dep = true;
+          dkey = (int64_t)k2 * g.nx + i2;
+        }
+      }
+    }
   }
-  int64_t node[4];
-  double W[4];
-  corners(g, i, k, x - (double)i, z - (double)k, node, W);
-  double B[3];
-  b_at(g, a.Hold, mover, x, z, i, k, B);
-  const double gam = gamma_bar(g, a.Eold, mover, sp.beta, u, node, W);
-  if (!PUSH) {
-    deposit_one(a, sp, s, gam, u, B, node, W, wp);
-    return;
+  // move counts and arrivals, then the moments, each summed over the lanes' runs
+  const Seg sd = seg_of(dep ? dkey : -1 - (int64_t)lane);
+  if (PUSH) {
+    const Seg sc = seg_of(cnt_on ? ckey : -1 - (int64_t)lane);
+    const int nc_ = seg_sum(sc, cnt_on ? 1 : 0);
+    if (cnt_on && sc.head) atomicAdd(&sp.cnt[cidx], nc_);
+    const int na_ = seg_sum(sd, dep ? 1 : 0);
+    if (dep && sd.head) atomicAdd(&sp.arr[dkey], na_);
   }
-  // E-bar at the particle and the implicit push: a = u + beta E-bar, b = beta B / gamma-bar,
-  // u-bar = (a + a x b + (a.b) b) / (1 + b.b), u' = 2 u-bar - u
   const int64_t nn = g.nnodes;
-  double Eb[3];
-  for (int r = 0; r < 3; ++r) {
-    const double *eo = a.Eold + r * nn, *en = a.Enew + r * nn;
-    double acc = 0.0;
-    for (int c = 0; c < 4; ++c) acc += W[c] * (0.5 * (eo[node[c]] + en[node[c]]));
-    Eb[r] = acc;
+  for (int c = 0; c < 4; ++c) {
+    for (int r = 0; r < 13; ++r) {
+      const double t = seg_sum(sd, W[c] * v[r]);
+      if (dep && sd.head) unsafeAtomicAdd(&a.M[(int64_t)(r < 12 ? r : 12 + s) * nn + node[c]], t);
+    }
   }
-  const double bx = sp.beta / gam * B[0], by = sp.beta / gam * B[1], bz = sp.beta / gam * B[2];
-  const double a0 = u[0] + sp.beta * Eb[0], a1 = u[1] + sp.beta * Eb[1], a2 = u[2] + sp.beta * Eb[2];
-  const double inv = 1.0 / (1.0 + bx * bx + by * by + bz * bz);
-  const double ab = a0 * bx + a1 * by + a2 * bz;
-  double un[3];
-  un[0] = 2.0 * ((a0 + (a1 * bz - a2 * by) + ab * bx) * inv) - u[0];
-  un[1] = 2.0 * ((a1 + (a2 * bx - a0 * bz) + ab * by) * inv) - u[1];
-  un[2] = 2.0 * ((a2 + (a0 * by - a1 * bx) + ab * bz) * inv) - u[2];
-  const double g1 = sqrt(1.0 + un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
-  double xn = x + g.cx * (un[0] / g1), zn = z + g.cz * (un[2] / g1);
-  bool alive = true;
-  if (g.bc_x == PIC_BC_PERIODIC) {
-    if (xn < 0.0) xn += (double)g.nx;
-    if (xn >= (double)g.nx) xn -= (double)g.nx;
-  } else if (xn < 0.0 || xn >= (double)g.nx) {
-    alive = false;
-  }
-  if (zn < 0.0) zn += (double)g.nz;
-  if (zn >= (double)g.nz) zn -= (double)g.nz;
-  const bool finite = isfinite(g1) && isfinite(xn) && isfinite(zn);
-  if (!finite) atomicOr(a.flags, kFlagNonFiniteA);
-  alive = alive && finite;
-  const int i2 = finite ? (int)floor(xn) : i, k2 = finite ? (int)floor(zn) : k;
-  int di = i2 - i, dk = k2 - k;
-  if (di > 1) di -= g.nx;
-  if (di < -1) di += g.nx;
-  if (dk > 1) dk -= g.nz;
-  if (dk < -1) dk += g.nz;
-  const bool jump = di < -1 || di > 1 || dk < -1 || dk > 1;
-  if (alive && jump) atomicOr(a.flags, kFlagJumpA);
-  alive = alive && !jump;
-  const uint32_t code = alive ? (uint32_t)((dk + 1) * 3 + (di + 1)) : kAbsorbed;
-  // the pushed state goes to location j of the other buffer; the sort reads the codes
-  sp.dst[0][j] = xn;
-  sp.dst[1][j] = zn;
-  sp.dst[2][j] = un[0];
-  sp.dst[3][j] = un[1];
-  sp.dst[4][j] = un[2];
-  if (sp.dst_id) sp.dst_id[j] = sp.src_id[p];
-  if (sp.w_stride) sp.dst_w[j] = wp;
-  sp.locode[j] = ((uint32_t)j << 4) | code;
-  if (!alive) return;
-  atomicAdd(&sp.cnt[(int64_t)code * g.ncells + (int64_t)k * g.nx + i], 1);
-  atomicAdd(&sp.arr[(int64_t)k2 * g.nx + i2], 1);
-  // the moments at x^{n+3/2} with u^{n+1}, B = H^{n+3/2} at the new position and E^{n+1}
-  int64_t node2[4];
-  double W2[4], B2[3];
-  corners(g, i2, k2, xn - (double)i2, zn - (double)k2, node2, W2);
-  b_at(g, a.Hnew, mover, xn, zn, i2, k2, B2);
-  const double gam2 = gamma_bar(g, a.Enew, mover, sp.beta, un, node2, W2);
-  deposit_one(a, sp, s, gam2, un, B2, node2, W2, wp);
 }
 
 // Energies: out[0] field, out[1 + s] kinetic of species s (both times dx dz), summed over
