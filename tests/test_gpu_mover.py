@@ -60,6 +60,29 @@ def test_mover_options_match_oracle(pic, wi, options):
     ctx.close()
 
 
+@pytest.mark.parametrize("options", [1, 3])
+def test_mover_options_dense_cells_per_particle_densities(pic, options):
+    """The options kernel sums each value over the lanes that deposit into one cell before its
+    global atomics.  100 particles per cell and species make runs of equal cells that fill
+    whole wavefronts and cross wavefront and block edges; three species with per-particle
+    densities and an absorbing x boundary (particles leave, the counts skip them)."""
+    base = picgen.random_small(77, nx=9, nz=6, ppc=100, bc_x=1, masses=(1.0, 25.0, 4.0),
+                               charges=(-1.0, 1.0, 2.0), temps=(20.0, 0.5, 2.0),
+                               density=(0.8, 0.4, 0.2))
+    wl = picgen.with_particle_densities(base, 77)
+    _say(f"mover options {options}, dense cells, per-particle densities")
+    ctx, orc = _setup(pic, wl, options, 77)
+    check_moments(ctx, orc)
+    for _ in range(2):
+        ctx.step(2)
+        orc.step(2)
+        check_fields(ctx, orc)
+        check_moments(ctx, orc)
+        check_particles(ctx, orc, wl)
+    assert ctx.get_info()["overflow_flags"] == 0
+    ctx.close()
+
+
 def test_mover_switch_mid_run(pic):
     """Options on for three cycles, then back to the default tile kernel (and the oracle's
     default mover) for three more."""
