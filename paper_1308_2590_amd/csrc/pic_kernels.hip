@@ -587,14 +587,18 @@ __device__ __forceinline__ void drain_movers(const MoverQ<T> &q, int count, int 
 template <typename T>
 __device__ __forceinline__ void deposit_one(const AccLds &acc, int o, int rc, T fx, T fz,
                                             const Compact<T> &m, T w, int dplane) {
-  const int rot = (threadIdx.x & 1) << 1;
-#pragma unroll 1
+  // odd lanes take the upper row of corners first (corners 2, 3, 0, 1)
+  const bool odd = threadIdx.x & 1;
+  const T gx[2] = {T(1) - fx, fx};
+  const T gz[2] = {odd ? fz : T(1) - fz, odd ? T(1) - fz : fz};
+  const int orow[2] = {o + (odd ? acc.LW : 0), o + (odd ? 0 : acc.LW)};
+  const int crow[2] = {odd ? 2 : 0, odd ? 0 : 2};
+#pragma unroll
   for (int c0 = 0; c0 < 4; ++c0) {
-    const int c = (c0 + rot) & 3;
-    const int cx = c & 1, cz = c >> 1;
-    const T W = (cx ? fx : T(1) - fx) * (cz ? fz : T(1) - fz);
-    corner_add(acc, o + cx + cz * acc.LW, rc, c, W * m.a0, W * m.a1, W * m.a2, W * m.j0, W * m.j1,
-               W * m.j2, W * w, dplane);
+    const int cx = c0 & 1, row = c0 >> 1;
+    const T W = gx[cx] * gz[row];
+    corner_add(acc, orow[row] + cx, rc, crow[row] + cx, W * m.a0, W * m.a1, W * m.a2, W * m.j0,
+               W * m.j1, W * m.j2, W * w, dplane);
   }
 }
 
