@@ -90,7 +90,7 @@ enum {
 };
 
 typedef struct {
-  int32_t nx, nz;            /* cells along x and z, each >= 1 */
+  int32_t nx, nz;            /* cells along x and z, each in 1 .. 2^22 - 1, nx nz < 2^31 - 1 */
   double dx, dz, dt;         /* cell sizes and time step; dt <= min(dx, dz) is required */
   int32_t bc_x, bc_z;        /* PIC_BC_*; bc_z must be PIC_BC_PERIODIC */
   int32_t precision;         /* PIC_PREC_FP64 or PIC_PREC_MIXED (see below) */

@@ -462,6 +462,9 @@ pic_status pic_init_grid(const pic_grid_desc *d, pic_ctx **out) {
     if (d->reserved[r] != 0) return fail(nullptr, PIC_ERR_ARG, "reserved fields must be zero");
   if (d->nx < 1 || d->nz < 1) return fail(nullptr, PIC_ERR_ARG, "nx and nz must be >= 1");
   if ((int64_t)d->nx * d->nz > 0x7fffffffLL - 1) return fail(nullptr, PIC_ERR_ARG, "too many cells");
+  // the kernels find a cell's tile by a float-reciprocal quotient, exact below 2^22
+  if (d->nx >= (1 << 22) || d->nz >= (1 << 22))
+    return fail(nullptr, PIC_ERR_ARG, "nx and nz must be below 2^22");
   if (!(d->dx > 0 && d->dz > 0 && d->dt > 0) || !std::isfinite(d->dx) || !std::isfinite(d->dz) ||
       !std::isfinite(d->dt))
     return fail(nullptr, PIC_ERR_ARG, "dx, dz, dt must be positive and finite");

@@ -64,9 +64,11 @@ __device__ __forceinline__ int wrap_t(int i, int n, bool near) {
   return near ? wrap1(i, n) : wrap_any(i, n);
 }
 
-// Quotient e / d of small non-negative integers (e < 2^16, 0 < d < 2^12) from one multiply:
-// (e + 1/2) / d lies at least 1 / (2 d) away from every integer, far more than the rounding of
-// the float product, so truncating it gives the exact quotient.
+// Quotient e / d of non-negative integers (e < 2^22, 0 < d < 2^12) from one multiply:
+// (e + 1/2) / d lies at least 1 / (2 d) away from every integer, and the float product is
+// within a relative 2^-23 of it, i.e. within (e + 1/2) / d 2^-23 < 1 / (2 d) absolutely, so
+// truncating it gives the exact quotient.  Grid coordinates (below 2^22 by the grid's limits)
+// and tile-local indices both qualify.
 struct SmallDiv {
   float r;
   __device__ __forceinline__ explicit SmallDiv(int d) : r(1.0f / (float)d) {}

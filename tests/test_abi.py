@@ -70,6 +70,7 @@ def _desc(**kw):
 @pytest.mark.parametrize("field,value,msg", [
     ("dt", 2.0, "dt must not exceed"),
     ("nx", 0, "nx and nz"),
+    ("nx", 1 << 22, "below 2^22"),
     ("bc_z", 1, "bc_z must be periodic"),
     ("precision", 7, "precision"),
     ("n_species", 9, "n_species"),
