@@ -179,3 +179,26 @@ def test_mover_options_full_foil_one_cycle(pic):
     check_particles(ctx, orc, wl)
     assert ctx.get_info()["overflow_flags"] == 0
     ctx.close()
+
+
+def test_mover_options_field_dominated_full_size_one_cycle(pic):
+    """The 2048 x 2048 run (33.6M particles at 4 per cell and species, the laser entering
+    through the absorbing x = 0 boundary) with both options: the deposit of the loaded state and
+    one full cycle against the oracle.  Runs of equal cells are short here (about four lanes),
+    the opposite of the foil's."""
+    wl = picgen.named("lowdensity")
+    _say(f"mover options, field-dominated full size {wl.n_particles} particles")
+    ctx = pic.Context(wl.grid, track_ids=False)
+    orc = OracleSim(wl.grid, mode=3)
+    for s, sp in enumerate(wl.species):
+        ctx.load_particles(s, sp.q, sp.m, sp.w, sp.xi_x, sp.xi_z, sp.ux, sp.uy, sp.uz)
+        orc.load_species(s, sp.q, sp.m, sp.w, sp.xi_x, sp.xi_z, sp.ux, sp.uy, sp.uz)
+    ctx.set_mover(3)
+    check_moments(ctx, orc)
+    ctx.step(1)
+    orc.step(1)
+    check_fields(ctx, orc)
+    check_moments(ctx, orc)
+    check_particles(ctx, orc, wl, ids=False)
+    assert ctx.get_info()["overflow_flags"] == 0
+    ctx.close()
