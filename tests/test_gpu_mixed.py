@@ -391,13 +391,13 @@ def test_mixed_full_size_foil_dense(pic):
     ctx.close()
 
 
-@pytest.mark.parametrize("name", ["foil_dense", "foil_dense_cm"])
+@pytest.mark.parametrize("name", ["foil_dense", "foil_dense_cm", "lowdensity"])
 def test_mixed_full_size_unlabelled(pic, name):
-    """The mixed-precision foil workloads at full size in the launch configuration the
-    benchmark times (automatic tiles, no particle labels): the geometry-literal dense foil
-    (40-cell slab, 5.24M particles) and the count-matched one (160-cell slab, 21.0M particles),
-    one cycle from identical state against the FP64 oracle, both sorted lists compared slot by
-    slot."""
+    """The mixed-precision workloads at full size in the launch configuration the benchmark
+    times (automatic tiles, no particle labels): the geometry-literal dense foil (40-cell slab,
+    5.24M particles), the count-matched one (160-cell slab, 21.0M particles) and the 2048 x 2048
+    run (33.6M particles, the chunk-of-2 form with its direct deposit), one cycle from
+    identical state against the FP64 oracle, both sorted lists compared slot by slot."""
     wl = picgen.fp32_representable(picgen.named(name))
     _say(f"mixed full size unlabelled {wl.name}: {wl.n_particles} particles")
     ctx, orc = setup_both(pic, wl, fields=picgen.random_fields(4, wl.grid), track_ids=False)
