@@ -495,6 +495,25 @@ def test_per_particle_densities(pic, wi, tile, ids):
     ctx.close()
 
 
+def test_per_particle_densities_field_dominated_full_size_one_cycle(pic):
+    """Per-particle densities on the 2048 x 2048 run (33.6M particles, the chunk-of-2 form with
+    the density carried through its direct deposit, the global deposit of particles leaving
+    their tile and the sort): the deposit of the loaded state and one cycle against the
+    oracle."""
+    wl = picgen.with_particle_densities(picgen.named("lowdensity"), seed=11)
+    _say(f"per-particle densities, field-dominated full size {wl.n_particles} particles")
+    ctx, orc = setup_both(pic, wl, track_ids=False)
+    check_moments(ctx, orc)
+    ctx.step(1)
+    orc.step(1)
+    check_fields(ctx, orc)
+    check_moments(ctx, orc)
+    check_particles(ctx, orc, wl, ids=False)
+    info = ctx.get_info()
+    assert info["overflow_flags"] == 0 and info["absorbed"] == orc.absorbed
+    ctx.close()
+
+
 def test_per_particle_densities_mixed_with_uniform_species(pic):
     """One species with per-particle densities and one with a single density in the same
     context (the kernels read the single density with stride 0), including reloading the
